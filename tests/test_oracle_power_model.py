@@ -1,0 +1,137 @@
+"""Pins for the power-model oracle (oracle/power_model.py): values of Eq. 2 /
+Eq. 3 worked by hand, closed forms of the energy optimum, exact recovery of
+known parameters, and a brute-force grid for the least-squares fit."""
+import numpy as np
+import pytest
+
+from oracle import power_model as pm
+
+M = dict(p_idle=100.0, alpha=0.2, beta=0.001, tau=1000.0, p_max=2000.0)
+
+
+def P(f, **kw):
+    m = dict(M, **kw)
+    return float(pm.power(f, m["p_idle"], m["alpha"], m["beta"], m["tau"], m["p_max"]))
+
+
+def test_eq2_eq3_hand_values():
+    # below tau: v = 1 -> 100 + 0.2*800 = 260
+    assert P(800.0) == pytest.approx(260.0, rel=1e-15)
+    # at tau: v = 1 (continuous reading) -> 100 + 0.2*1000 = 300
+    assert P(1000.0) == pytest.approx(300.0, rel=1e-15)
+    # above: v = 1 + 0.001*500 = 1.5 -> 100 + 0.2*1500*2.25 = 775
+    assert P(1500.0) == pytest.approx(775.0, rel=1e-15)
+    # clipped: 100 + 0.2*2400*(2.4)^2 = 2864.8 -> P_max 2000
+    assert P(2400.0) == pytest.approx(2000.0, rel=1e-15)
+
+
+def test_literal_eq3_is_discontinuous_at_tau():
+    v_lo = float(pm.voltage(999.999, 0.001, 1000.0, literal=True))
+    v_at = float(pm.voltage(1000.0, 0.001, 1000.0, literal=True))
+    assert v_lo == 1.0 and v_at == 0.0
+    v_at_cont = float(pm.voltage(1000.0, 0.001, 1000.0))
+    assert v_at_cont == 1.0
+
+
+def test_beta_zero_gives_race_to_idle():
+    # beta = 0: E*(f) = P_idle/f + alpha decreases -> f* = f_max
+    m = dict(M, beta=0.0)
+    settable = np.arange(500.0, 2401.0, 25.0)
+    assert pm.optimal_clock(settable, m) == 2400.0
+
+
+def test_optimum_at_or_above_tau():
+    settable = np.arange(300.0, 2401.0, 5.0)
+    f_opt = pm.optimal_clock(settable, M)
+    assert f_opt >= M["tau"]
+
+
+def test_interior_optimum_solves_stationarity():
+    # For f > tau and unclipped: d/df (P_idle/f + alpha*v^2) = 0
+    #   <=> P_idle / f^2 = 2 * alpha * beta * (1 + beta*(f - tau))
+    from scipy.optimize import brentq
+    m = dict(p_idle=2000.0, alpha=0.15, beta=0.002, tau=900.0, p_max=1e9)
+    g = lambda f: m["p_idle"] / f ** 2 - 2 * m["alpha"] * m["beta"] * (1 + m["beta"] * (f - m["tau"]))  # noqa: E731
+    assert g(m["tau"]) > 0  # the optimum lies strictly above tau
+    root = brentq(g, m["tau"], 5000.0)
+    settable = np.arange(500.0, 2500.0, 0.01)
+    f_opt = pm.optimal_clock(settable, m)
+    assert abs(f_opt - root) <= 0.011
+
+
+def test_flat_tie_goes_to_highest_clock():
+    # P_idle = 0: E* = alpha below tau (flat) and rises above -> highest flat clock = tau
+    m = dict(p_idle=0.0, alpha=0.5, beta=0.01, tau=1200.0, p_max=1e9)
+    settable = np.arange(500.0, 2001.0, 100.0)
+    assert pm.optimal_clock(settable, m) == 1200.0
+
+
+def test_clipping_region_is_p_max_over_f():
+    f = np.array([2300.0, 2400.0])
+    e = pm.energy_estimate(f, M)
+    np.testing.assert_allclose(e, 2000.0 / f, rtol=1e-15)
+
+
+def test_band_closed_form():
+    settable = np.arange(100.0, 2401.0, 100.0)
+    assert pm.clock_band(settable, 1500.0) == [1400.0, 1500.0, 1600.0]
+    # endpoints are inclusive: 0.9*1000 = 900, 1.1*1000 = 1100
+    assert pm.clock_band(settable, 1000.0) == [900.0, 1000.0, 1100.0]
+    # clamped to the settable range
+    assert pm.clock_band(settable, 2400.0) == [2200.0, 2300.0, 2400.0]
+
+
+def _synthetic(f, m):
+    return pm.power(f, m["p_idle"], m["alpha"], m["beta"], m["tau"], m["p_max"])
+
+
+@pytest.mark.parametrize("m", [
+    dict(p_idle=180.0, alpha=0.12, beta=0.0012, tau=1350.0, p_max=5000.0),
+    dict(p_idle=90.0, alpha=0.08, beta=0.0020, tau=1100.0, p_max=5000.0),
+])
+def test_fit_recovers_known_parameters_noise_free(m):
+    f = np.linspace(500.0, 2400.0, 9)
+    p = _synthetic(f, m)
+    r = pm.fit(f, p, m["p_max"])
+    for k in ("p_idle", "alpha", "beta"):
+        assert r[k] == pytest.approx(m[k], rel=1e-6), k
+    assert r["tau"] == pytest.approx(m["tau"], rel=1e-6)
+    assert r["sse"] < 1e-12
+
+
+def test_fit_five_points_recovers():
+    m = dict(p_idle=150.0, alpha=0.1, beta=0.0015, tau=1000.0, p_max=5000.0)
+    f = np.array([500.0, 975.0, 1450.0, 1925.0, 2400.0])
+    p = _synthetic(f, m)
+    r = pm.fit(f, p, m["p_max"])
+    assert r["sse"] < 1e-10
+    # identifiable: 2 points at or below tau fix (P_idle, alpha), 3 above fix (beta, tau)
+    assert r["p_idle"] == pytest.approx(150.0, rel=1e-5)
+    assert r["alpha"] == pytest.approx(0.1, rel=1e-5)
+
+
+def test_fit_noisy_not_worse_than_bruteforce_grid():
+    rng = np.random.default_rng(0)
+    m = dict(p_idle=200.0, alpha=0.15, beta=0.0010, tau=1500.0, p_max=5000.0)
+    f = np.linspace(600.0, 2400.0, 7)
+    p = _synthetic(f, m) + rng.normal(0.0, 5.0, f.size)
+    r = pm.fit(f, p, m["p_max"])
+    # independent brute force: dense 4-D grid around the truth
+    best = np.inf
+    for pi in np.linspace(150, 250, 21):
+        for al in np.linspace(0.10, 0.20, 21):
+            for b in np.linspace(0.0, 0.002, 21):
+                for t in np.linspace(1200, 1800, 25):
+                    v = np.where(f >= t, 1 + b * (f - t), 1.0)
+                    res = p - np.minimum(m["p_max"], pi + al * f * v * v)
+                    best = min(best, float(res @ res))
+    assert r["sse"] <= best * (1 + 1e-9)
+
+
+def test_fit_with_measured_voltage_is_linear_least_squares():
+    f = np.array([600.0, 1000.0, 1400.0, 1800.0, 2200.0])
+    v = np.array([0.70, 0.70, 0.78, 0.90, 1.05])
+    p = 120.0 + 0.3 * f * v * v
+    r = pm.fit(f, p, 1e9, v=v)
+    assert r["p_idle"] == pytest.approx(120.0, rel=1e-9)
+    assert r["alpha"] == pytest.approx(0.3, rel=1e-9)
