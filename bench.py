@@ -1,0 +1,162 @@
+"""Benchmark: tuned FP32 2-D cross-correlation on one MI355X.
+
+Workload: single-channel FP32 cross-correlation, output 4096 x 4096, filter
+17 x 17, input 4112 x 4112, uniform[0,1) from seed 0 (synthetic).  One step =
+one launch of the kernel with the tuned configuration, inputs resident in HBM.
+The energy efficiency (GFLOP/s/W) of the same configuration is measured after
+the timed region with the library's measure_time_energy (median socket power
+times time per run).  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3    # MI355X published FP32 vector peak (packed FMA, 2.4 GHz)
+FP32_NONPACKED_PEAK_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 flop x 2.4 GHz (one FMA per lane per clock)
+TUNED = os.path.join(ROOT, "paper_2211_07260_amd", "tuned", "xcorr_f32_4096x4096_f17.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "xcorr_f32_4096x4096_f17_traffic.json")
+DEFAULT_CFG = (32, 8, 4, 4, 0, 0)
+
+
+def load_tuned():
+    if os.path.exists(TUNED):
+        with open(TUNED) as fh:
+            return json.load(fh)
+    return None
+
+
+def cpu_baseline(img, w, min_seconds=8.0):
+    """The FP64 oracle on the host cores over the full workload, repeated until
+    about min_seconds have passed."""
+    import oracle
+    nthreads = min(16, os.cpu_count() or 1)
+    flops = 2.0 * 4096 * 4096 * 17 * 17
+    a, b = img.numpy(), w.numpy()
+    oracle.xcorr2d(a[:64 + 16, :], b, nthreads=nthreads)  # load + warm
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        oracle.xcorr2d(a, b, nthreads=nthreads)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= min_seconds:
+            break
+    return {"value": flops * reps / el / 1e9, "unit": "GFLOP/s", "cores": nthreads, "kind": "oracle",
+            "sample": "full 4096x4096x17x17 FP64 cross-correlation x%d (%.1f s wall)" % (reps, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-energy", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--config", type=str, default=None, help="bx,by,tx,ty,pad,rp")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the tuning method and its kernels run on a single "
+              "device; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2211_07260_amd as gt
+    from synthetic import xcorr_inputs
+
+    tuned = load_tuned()
+    if args.config:
+        cfg = tuple(int(v) for v in args.config.split(","))
+        cfg_src = "command line"
+    elif tuned:
+        cfg = tuple(tuned["time_optimal"]["config"])
+        cfg_src = "time-optimal config of the committed sweep"
+    else:
+        cfg = DEFAULT_CFG
+        cfg_src = "default (no committed sweep)"
+
+    dev = torch.device("cuda:0")
+    gt.init(0, 0)
+    img, w = xcorr_inputs(4096, 4096, 17, 17, seed=0)
+    d_in, d_w = img.to(dev), w.to(dev)
+    out = torch.empty(4096, 4096, dtype=torch.float32, device=dev)
+    prob = gt.xcorr_problem(4096, 4096, 17, 17)
+    flops = gt.problem_flops(prob)
+
+    for _ in range(args.warmup):
+        gt.conv2d_run(prob, cfg, d_in, d_w, out)
+    torch.cuda.synchronize()
+    print("bench: warmup done, config %s (%s)" % (cfg, cfg_src), file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        gt.conv2d_run(prob, cfg, d_in, d_w, out, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall0
+    ms = e0.elapsed_time(e1) / args.steps
+    gflops = flops / (ms * 1e-3) / 1e9
+    print("bench: timed %d steps, %.4f ms/step, %.1f GFLOP/s" % (args.steps, ms, gflops),
+          file=sys.stderr, flush=True)
+
+    energy = None
+    if not args.no_energy:
+        try:
+            m = gt.measure_time_energy(prob, cfg, d_in, d_w, out, window_s=1.0, discard_s=0.3)
+            energy = {"gflops_per_w": m["gflops_per_w"], "gflops": m["gflops"], "p_median_w": m["p_median_w"],
+                      "e_run_j": m["e_run_j"], "e_run_counter_j": m["e_run_counter_j"],
+                      "sclk_act_mhz": m["sclk_act_mhz"], "temp_c": m["temp_c"], "n_samples": m["n_used"]}
+            print("bench: energy %.2f GFLOP/s/W at %.0f W" % (m["gflops_per_w"], m["p_median_w"]),
+                  file=sys.stderr, flush=True)
+        except gt.GreentuneError as e:
+            energy = {"error": str(e)}
+
+    traffic = None
+    if os.path.exists(TRAFFIC):
+        with open(TRAFFIC) as fh:
+            t = json.load(fh)
+        if tuple(t.get("config", ())) == tuple(cfg):
+            traffic = t.get("hbm_bytes_per_launch")
+
+    achieved = flops / (ms * 1e-3) / 1e12
+    result = {
+        "metric": "GFLOP/s/W and GFLOP/s of tuned conv2d; clocks measured vs full sweep; p99 ms",
+        "value": round(gflops, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "xcorr2d FP32 single-channel, out 4096x4096, filter 17x17, uniform[0,1) seed 0",
+                   "kernel_config": dict(zip(gt.CONFIG_FIELDS, cfg)), "config_source": cfg_src,
+                   "parallelism": "single GPU"},
+        "gflops_per_w": energy.get("gflops_per_w") if energy and "gflops_per_w" in energy else None,
+        "energy": energy,
+        "wall_s_timed": round(t_wall, 4),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                     "frac_of_nonpacked_peak": round(achieved / FP32_NONPACKED_PEAK_TFLOPS, 4),
+                     "traffic": traffic},
+    }
+    if tuned:
+        result["tuning"] = {k: tuned[k] for k in tuned if k not in ("rows",)}
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(img, w)
+    gt.shutdown()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,247 @@
+/*
+ * greentune -- energy-aware auto-tuning of a parameterised 2-D convolution on
+ * one MI355X (gfx950).  C ABI: plain pointers and sizes only.
+ *
+ * The method is the one of "Going green: optimizing GPUs for energy
+ * efficiency through model-steered auto-tuning" (Schoonhoven, Veenboer,
+ * van Werkhoven, Batenburg, 2022):
+ *   - every kernel configuration of a restricted tune space is launched and
+ *     measured for time and energy (sections III.B, III.C, IV);
+ *   - energy is a representative (median) power reading times elapsed time
+ *     (section III.A);
+ *   - a power-versus-clock model, Eq. 2 with the voltage estimate of Eq. 3,
+ *     is fitted by Levenberg-Marquardt least squares to a few power readings
+ *     (sections III.A and V.D), and the clock search is cut to +-10 % around
+ *     the clock where the model's energy estimate P*(f)/f is lowest.
+ *
+ * Conventions for every function below:
+ *   - returns GT_OK (0) or a negative GT_E_* code; gt_last_error() then gives
+ *     a message (thread-local, valid until the next call on that thread);
+ *   - the caller owns every buffer.  Device pointers are plain HIP device
+ *     addresses (e.g. torch tensor data pointers); hip_stream is a
+ *     hipStream_t (NULL = the null stream).  The library keeps no reference
+ *     to a caller buffer after the call returns;
+ *   - all row-major arrays are dense (pitch = width).
+ */
+#ifndef GREENTUNE_H
+#define GREENTUNE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---- */
+#define GT_OK             0
+#define GT_E_INVAL       -1  /* bad argument (null pointer, size, enum) */
+#define GT_E_UNSUPPORTED -2  /* configuration outside the kernel's limits (threads, LDS, filter width) */
+#define GT_E_PERM        -3  /* DVFS change not permitted (or not allowed by gt_init flags) */
+#define GT_E_SENSOR      -4  /* no power sensor, or stale readings */
+#define GT_E_HIP         -5  /* HIP runtime error */
+#define GT_E_NOMEM       -6  /* host allocation failed */
+#define GT_E_CAPACITY    -7  /* output array too small; the *n_total style outputs are still written */
+#define GT_E_STATE       -8  /* library not initialised, or a GPU call in host-only mode */
+
+/* ---- problem kinds ---- */
+#define GT_XCORR_F32        0  /* single-channel FP32 cross-correlation, valid region */
+#define GT_IGEMM_BF16_MFMA  1  /* multi-channel NHWC conv, BF16 in, FP32 accumulate, MFMA */
+#define GT_IGEMM_F32_VALU   2  /* the same contraction in FP32 on the vector ALUs */
+
+/* A tunable kernel configuration (section IV: thread-block dimensions, work
+ * per thread, shared-memory use and read path are the tunable style).
+ *   block_size_x/y   workgroup shape in threads; bx*by <= 1024
+ *   tile_size_x/y    outputs per thread along x / y (1..8)
+ *   use_lds_padding  0/1: pad each LDS row by 4 floats
+ *   read_path        0: stage the input halo in LDS; 1: read global memory directly
+ * For the implicit-GEMM kinds only block_size_x (and read_path = 0) is used;
+ * see conv2d_run. */
+typedef struct {
+    int32_t block_size_x, block_size_y, tile_size_x, tile_size_y, use_lds_padding, read_path;
+} gt_conv_config;
+
+/* Problem description.
+ * GT_XCORR_F32: n = c_in = c_out = 1, pad = 0.  Input (out_h+filt_h-1) x
+ *   (out_w+filt_w-1) FP32, filter filt_h x filt_w FP32, output out_h x out_w FP32:
+ *   out[y][x] = sum_{i,j} in[y+i][x+j] * w[i][j]   (no filter flip).
+ * GT_IGEMM_*: stride 1, zero padding pad_h/pad_w; input NHWC [n][H][W][c_in]
+ *   with H = out_h + filt_h - 1 - 2*pad_h (likewise W); weights KRSC
+ *   [c_out][filt_h][filt_w][c_in]; output NHWC FP32 [n][out_h][out_w][c_out]:
+ *   out[b][y][x][k] = sum_{r,s,c} in[b][y+r-pad_h][x+s-pad_w][c] * wt[k][r][s][c].
+ *   Input and weights are BF16 for GT_IGEMM_BF16_MFMA and FP32 for GT_IGEMM_F32_VALU. */
+typedef struct {
+    int32_t kind;
+    int32_t n, c_in, c_out, out_h, out_w, filt_h, filt_w, pad_h, pad_w;
+} gt_problem;
+
+/* DVFS knob (section III.C: clock frequency or power limit as tunables). */
+#define GT_CLOCK_DEFAULT     0  /* leave DVFS untouched; value ignored */
+#define GT_CLOCK_SCLK_MHZ    1  /* upper limit of the graphics clock, MHz */
+#define GT_CLOCK_POWER_CAP_W 2  /* socket power cap, W */
+typedef struct { int32_t kind; int32_t value; } gt_clock;
+
+/* Tune-space descriptor: one value list per tunable (order as in
+ * gt_conv_config).  Enumeration is the Cartesian product in that order, last
+ * parameter fastest, filtered by the restrictions (section IV). */
+#define GT_SPACE_DEDUP_DIRECT 1u  /* drop read_path=1 with use_lds_padding=1 (same kernel) */
+typedef struct {
+    const int32_t *values[6];
+    int32_t counts[6];
+    uint32_t flags;
+    int32_t max_threads;      /* 0 = device limit (1024) */
+    int64_t lds_limit_bytes;  /* 0 = device's max shared memory per block (needs gt_init) */
+} gt_space_desc;
+
+/* Measurement options (section III.B: the kernel is repeated for a window,
+ * 1 s by default, because the sensor refreshes slowly and settles late). */
+typedef struct {
+    double window_s;          /* timed window; <= 0 -> 1.0 */
+    double discard_s;         /* leading samples dropped before the median; < 0 -> 0.3 */
+    double sample_period_ms;  /* sensor poll period; <= 0 -> 1.0 */
+    int32_t min_launches;     /* at least this many launches; <= 0 -> 10 */
+    int32_t warmup_launches;  /* untimed launches first; < 0 -> 3 */
+} gt_measure_opts;
+
+/* One measurement (section III.B observer fields; section III.C metrics). */
+typedef struct {
+    double t_run_s;           /* mean time per launch over the window (HIP events) */
+    double p_median_w;        /* median socket power over the kept samples */
+    double p_min_w, p_max_w;
+    double e_run_j;           /* p_median_w * t_run_s */
+    double e_run_counter_j;   /* energy-counter delta over the window / launches */
+    double gflops;            /* flops / t_run / 1e9 */
+    double gflops_per_w;      /* flops / e_run / 1e9  (= GFLOP/J) */
+    double sclk_req_mhz;      /* requested clock limit (0 = default) */
+    double sclk_act_mhz;      /* mean reported graphics clock over kept samples */
+    double mclk_mhz;          /* memory clock */
+    double volt_v;            /* graphics voltage, NaN if not reported */
+    double temp_c;            /* hotspot temperature at the end of the window */
+    double window_s;          /* actual timed window */
+    int64_t launches, n_samples, n_used;
+    int32_t throttled;        /* actual clock > 2 % below the requested limit */
+    int32_t flags;            /* bit 0: fake sensor, bit 1: fake DVFS */
+} gt_measurement;
+
+/* Fitted power model, Eq. 2 with Eq. 3:
+ *   P*(f) = min(p_max, p_idle + alpha * f * v(f)^2),
+ *   v(f)  = 1 for f < tau, 1 + beta * (f - tau) for f >= tau   (f in MHz).
+ * The printed Eq. 3 is discontinuous at tau; literal_eq3 = 1 evaluates it as
+ * printed (v = beta * (f - tau) above tau).  With measured voltage
+ * (v_measured = 1) beta and tau are unused and v comes from the readings. */
+typedef struct {
+    double p_idle, alpha, beta, tau_mhz, p_max;
+    double rss;               /* residual sum of squares of the fit, W^2 */
+    int32_t v_measured, literal_eq3, iters, status;  /* status 0 = converged */
+} gt_power_model;
+
+/* One sensor reading. */
+typedef struct {
+    double t_s;               /* host steady clock, seconds */
+    double power_w;           /* current socket power */
+    double energy_j;          /* energy accumulator (monotone, wraps are unwrapped) */
+    double sclk_mhz, mclk_mhz, volt_v, temp_c;
+} gt_sensor_sample;
+
+/* ---- lifecycle ---- */
+#define GT_INIT_FAKE_SENSOR 1u  /* synthetic power: P*(f) of gt_fake_sensor_model at the set clock */
+#define GT_INIT_FAKE_DVFS   2u  /* clock knob is recorded, hardware untouched */
+#define GT_INIT_ALLOW_DVFS  4u  /* permit real DVFS changes (needs privileges) */
+#define GT_INIT_HOST_ONLY   8u  /* no HIP calls at all (host arithmetic only) */
+
+/* Select the HIP device, open the power sensor (amd-smi) and DVFS controller.
+ * Idempotent for the same arguments.  Errors: GT_E_HIP (no such device),
+ * GT_E_SENSOR is NOT returned here -- a missing sensor is reported by the
+ * first measurement. */
+int gt_init(int device_ordinal, uint32_t flags);
+/* Restore any DVFS change made through the library, stop the sensor. */
+int gt_shutdown(void);
+const char *gt_last_error(void);
+/* Library version string. */
+const char *gt_version(void);
+
+/* ---- the four calls of the method ---- */
+
+/* Launch one convolution asynchronously on hip_stream.
+ * problem/config as above; clock: knob applied first (synchronously, only if
+ * it differs from the current setting; GT_CLOCK_DEFAULT never touches DVFS).
+ * d_in, d_filt, d_out: device pointers laid out as in gt_problem.
+ * Errors: GT_E_INVAL (null pointer, sizes), GT_E_UNSUPPORTED (config outside
+ * the restricted space or filter width not instantiated: single-channel
+ * filt_w in {3,5,9,17} with tile sizes 1..8), GT_E_PERM (clock knob
+ * refused), GT_E_HIP (launch failure). */
+int conv2d_run(const gt_problem *problem, const gt_conv_config *config, gt_clock clock,
+               const void *d_in, const void *d_filt, void *d_out, void *hip_stream);
+
+/* Enumerate the restricted tune space (section IV) into out[0..capacity).
+ * *n_total always receives the full count; GT_E_CAPACITY if capacity is too
+ * small (call with capacity 0 to size the array). */
+int tune_space_enumerate(const gt_problem *problem, const gt_space_desc *space,
+                         gt_conv_config *out, size_t capacity, size_t *n_total);
+
+/* Measure time and energy of one (problem, config, clock) point (sections
+ * III.A-III.B): apply the clock, run warm-up launches, then launch
+ * back-to-back on hip_stream for the window while a sampler thread polls the
+ * power sensor; t_run from HIP events, energy = median power of the samples
+ * after discard_s times t_run, cross-checked with the energy counter.
+ * Blocks until done; exclusive use of the device is assumed.
+ * Errors: as conv2d_run, plus GT_E_SENSOR (no usable samples). */
+int measure_time_energy(const gt_problem *problem, const gt_conv_config *config, gt_clock clock,
+                        const gt_measure_opts *opts, const void *d_in, const void *d_filt,
+                        void *d_out, void *hip_stream, gt_measurement *rec);
+
+/* Levenberg-Marquardt least-squares fit of Eq. 2 (+ Eq. 3 unless v_or_null
+ * is given) to n readings (f_mhz[i], p_w[i]).  p_max_w is held fixed (the
+ * paper takes it from the measured maximum or the TDP).  Host-only, FP64.
+ * Bounds: p_idle, alpha, beta >= 0; tau within [min f, max f].  Needs n >= 2
+ * with measured voltage, n >= 4 otherwise.  Errors: GT_E_INVAL. */
+int fit_power_model(const double *f_mhz, const double *p_w, const double *v_or_null, size_t n,
+                     double p_max_w, gt_power_model *out);
+
+/* ---- helpers of the method ---- */
+
+/* P*(f) of a fitted model (Eq. 2/3); NaN on a null model. */
+double gt_power_model_eval(const gt_power_model *model, double f_mhz);
+/* Model-optimal clock: argmin over settable[0..n) of P*(f)/f (the energy
+ * estimate of section V.D); ties (relative gap <= 1e-12) go to the higher
+ * clock.  Then the band: the settable clocks within [(1-rel_half) f_opt,
+ * (1+rel_half) f_opt], ascending (rel_half = 0.1 in the paper).
+ * GT_E_CAPACITY if cap is too small (*n_band still written). */
+int gt_power_model_band(const gt_power_model *model, const double *settable, size_t n,
+                        double rel_half, double *f_opt, double *band, size_t cap, size_t *n_band);
+/* Energy per run from a power trace (section III.A): median of the samples
+ * with t_start + discard_s <= t <= t_stop (mean of the middle two for an even
+ * count) times (t_stop - t_start) / n_runs.  GT_E_SENSOR if no sample is kept. */
+int gt_energy_from_samples(const double *t_s, const double *p_w, size_t n, double t_start,
+                           double t_stop, int64_t n_runs, double discard_s, double *e_run_j,
+                           double *p_median_w, size_t *n_used);
+/* Objective selection over a measurement table (section V.A):
+ * objective 0 = time (race-to-idle): min t_run, then e_run, then index;
+ * objective 1 = energy: min e_run, then t_run, then index. */
+int gt_select(const gt_measurement *recs, size_t n, int objective, size_t *index);
+/* Algorithmic flop count: 2 per filter tap per output (padded taps counted). */
+double gt_problem_flops(const gt_problem *problem);
+/* LDS bytes the config's workgroup allocates (0 for read_path 1 and for the
+ * implicit-GEMM kinds' fixed tiles, which report their own static size). */
+int gt_conv_lds_bytes(const gt_problem *problem, const gt_conv_config *config, int64_t *bytes);
+
+/* ---- sensor and DVFS ---- */
+
+/* One reading of the power sensor (amd-smi GPU metrics, or the fake sensor). */
+int gt_sensor_read(gt_sensor_sample *s);
+/* Settable graphics-clock list in MHz, ascending (DVFS range of the device,
+ * at step_mhz spacing; the fake DVFS backend reports 500..2400).
+ * GT_E_CAPACITY if cap is too small (*n still written). */
+int gt_settable_clocks(double step_mhz, double *mhz, size_t cap, size_t *n);
+/* Current DVFS state: 1 if a knob set through the library is active. */
+int gt_dvfs_state(gt_clock *current);
+/* Synthetic power for GT_INIT_FAKE_SENSOR: readings follow the model at the
+ * clock the (fake or real) DVFS controller reports, plus zero-mean noise of
+ * the given standard deviation (deterministic, seeded).  Idle power applies
+ * when no kernel is running in the window. */
+int gt_fake_sensor_model(const gt_power_model *model, double noise_w, uint64_t seed);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GREENTUNE_H */

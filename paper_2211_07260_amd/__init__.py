@@ -1,0 +1,342 @@
+"""greentune: energy-aware auto-tuning of a parameterised 2-D convolution on
+one MI355X, after "Going green: optimizing GPUs for energy efficiency through
+model-steered auto-tuning".
+
+This module is a thin ctypes binding over ``libgreentune.so`` (C ABI in
+``include/greentune.h``): it marshals arguments and nothing else.  Every step
+of the method runs in the native library and its HIP kernels; torch tensors
+only provide device memory and streams.  If the native library is missing the
+import fails loudly -- there is no fallback.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgreentune.so")
+
+# ---- constants mirrored from include/greentune.h ----
+GT_OK, GT_E_INVAL, GT_E_UNSUPPORTED, GT_E_PERM = 0, -1, -2, -3
+GT_E_SENSOR, GT_E_HIP, GT_E_NOMEM, GT_E_CAPACITY, GT_E_STATE = -4, -5, -6, -7, -8
+XCORR_F32, IGEMM_BF16_MFMA, IGEMM_F32_VALU = 0, 1, 2
+CLOCK_DEFAULT, CLOCK_SCLK_MHZ, CLOCK_POWER_CAP_W = 0, 1, 2
+SPACE_DEDUP_DIRECT = 1
+INIT_FAKE_SENSOR, INIT_FAKE_DVFS, INIT_ALLOW_DVFS, INIT_HOST_ONLY = 1, 2, 4, 8
+CONFIG_FIELDS = ("block_size_x", "block_size_y", "tile_size_x", "tile_size_y",
+                 "use_lds_padding", "read_path")
+
+
+class GreentuneError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("greentune error %d: %s" % (code, msg))
+        self.code = code
+
+
+class ConvConfig(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in CONFIG_FIELDS]
+
+    def as_tuple(self):
+        return tuple(getattr(self, n) for n in CONFIG_FIELDS)
+
+    def __repr__(self):
+        return "ConvConfig(%s)" % ", ".join("%s=%d" % (n, getattr(self, n)) for n in CONFIG_FIELDS)
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("kind", "n", "c_in", "c_out", "out_h", "out_w",
+                                             "filt_h", "filt_w", "pad_h", "pad_w")]
+
+
+class Clock(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("value", ctypes.c_int32)]
+
+
+class SpaceDesc(ctypes.Structure):
+    _fields_ = [("values", ctypes.POINTER(ctypes.c_int32) * 6), ("counts", ctypes.c_int32 * 6),
+                ("flags", ctypes.c_uint32), ("max_threads", ctypes.c_int32),
+                ("lds_limit_bytes", ctypes.c_int64)]
+
+
+class MeasureOpts(ctypes.Structure):
+    _fields_ = [("window_s", ctypes.c_double), ("discard_s", ctypes.c_double),
+                ("sample_period_ms", ctypes.c_double), ("min_launches", ctypes.c_int32),
+                ("warmup_launches", ctypes.c_int32)]
+
+
+_MEAS_D = ("t_run_s", "p_median_w", "p_min_w", "p_max_w", "e_run_j", "e_run_counter_j", "gflops",
+           "gflops_per_w", "sclk_req_mhz", "sclk_act_mhz", "mclk_mhz", "volt_v", "temp_c", "window_s")
+
+
+class Measurement(ctypes.Structure):
+    _fields_ = ([(n, ctypes.c_double) for n in _MEAS_D]
+                + [("launches", ctypes.c_int64), ("n_samples", ctypes.c_int64), ("n_used", ctypes.c_int64),
+                   ("throttled", ctypes.c_int32), ("flags", ctypes.c_int32)])
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class PowerModel(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("p_idle", "alpha", "beta", "tau_mhz", "p_max", "rss")] + \
+               [(n, ctypes.c_int32) for n in ("v_measured", "literal_eq3", "iters", "status")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class SensorSample(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("t_s", "power_w", "energy_j", "sclk_mhz", "mclk_mhz",
+                                               "volt_v", "temp_c")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+def _hip_runtimes():
+    try:
+        with open("/proc/self/maps") as fh:
+            maps = fh.read()
+    except OSError:
+        return set()
+    return {ln.split()[-1] for ln in maps.splitlines() if "libamdhip64" in ln}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libgreentune.so is not built (run paper_2211_07260_amd/build.py)")
+    # torch's HIP runtime must be the one the library binds to: load it first so
+    # the library's libamdhip64 dependency resolves to the already-loaded copy.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIB_PATH)
+    rts = _hip_runtimes()
+    if len(rts) > 1:
+        raise ImportError("two HIP runtimes are loaded (%s); the library must share torch's" % sorted(rts))
+    P, c_int, c_double, c_size = ctypes.POINTER, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    vp = ctypes.c_void_p
+    sig = {
+        "gt_init": ([c_int, ctypes.c_uint32], c_int),
+        "gt_shutdown": ([], c_int),
+        "gt_last_error": ([], ctypes.c_char_p),
+        "gt_version": ([], ctypes.c_char_p),
+        "conv2d_run": ([P(Problem), P(ConvConfig), Clock, vp, vp, vp, vp], c_int),
+        "tune_space_enumerate": ([P(Problem), P(SpaceDesc), P(ConvConfig), c_size, P(c_size)], c_int),
+        "measure_time_energy": ([P(Problem), P(ConvConfig), Clock, P(MeasureOpts), vp, vp, vp, vp,
+                                 P(Measurement)], c_int),
+        "fit_power_model": ([P(c_double), P(c_double), P(c_double), c_size, c_double, P(PowerModel)], c_int),
+        "gt_power_model_eval": ([P(PowerModel), c_double], c_double),
+        "gt_power_model_band": ([P(PowerModel), P(c_double), c_size, c_double, P(c_double), P(c_double),
+                                 c_size, P(c_size)], c_int),
+        "gt_energy_from_samples": ([P(c_double), P(c_double), c_size, c_double, c_double, ctypes.c_int64,
+                                    c_double, P(c_double), P(c_double), P(c_size)], c_int),
+        "gt_select": ([P(Measurement), c_size, c_int, P(c_size)], c_int),
+        "gt_problem_flops": ([P(Problem)], c_double),
+        "gt_conv_lds_bytes": ([P(Problem), P(ConvConfig), P(ctypes.c_int64)], c_int),
+        "gt_sensor_read": ([P(SensorSample)], c_int),
+        "gt_settable_clocks": ([c_double, P(c_double), c_size, P(c_size)], c_int),
+        "gt_dvfs_state": ([P(Clock)], c_int),
+        "gt_fake_sensor_model": ([P(PowerModel), c_double, ctypes.c_uint64], c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("gt_init", "gt_shutdown", "gt_last_error", "gt_version", "conv2d_run",
+            "tune_space_enumerate", "measure_time_energy", "fit_power_model", "gt_power_model_eval",
+            "gt_power_model_band", "gt_energy_from_samples", "gt_select", "gt_problem_flops",
+            "gt_conv_lds_bytes", "gt_sensor_read", "gt_settable_clocks", "gt_dvfs_state",
+            "gt_fake_sensor_model")
+
+
+def lib():
+    return _lib
+
+
+def _check(rc):
+    if rc != GT_OK:
+        raise GreentuneError(rc, _lib.gt_last_error().decode())
+    return rc
+
+
+def _darr(values):
+    vals = [float(v) for v in values]
+    return (ctypes.c_double * max(len(vals), 1))(*vals), len(vals)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+# ---- problems and configs ----
+
+def xcorr_problem(out_h, out_w, fh, fw):
+    return Problem(XCORR_F32, 1, 1, 1, out_h, out_w, fh, fw, 0, 0)
+
+
+def conv_problem(kind, n, h, w, c_in, c_out, fh, fw):
+    """Multi-channel conv, stride 1, same padding (output h x w)."""
+    return Problem(kind, n, c_in, c_out, h, w, fh, fw, (fh - 1) // 2, (fw - 1) // 2)
+
+
+def config(block_size_x=32, block_size_y=8, tile_size_x=4, tile_size_y=4, use_lds_padding=0, read_path=0):
+    return ConvConfig(block_size_x, block_size_y, tile_size_x, tile_size_y, use_lds_padding, read_path)
+
+
+def as_config(c):
+    if isinstance(c, ConvConfig):
+        return c
+    if isinstance(c, dict):
+        return config(**c)
+    return ConvConfig(*c)
+
+
+def clock(kind=CLOCK_DEFAULT, value=0):
+    return Clock(kind, int(value))
+
+
+# ---- lifecycle ----
+
+def init(device=0, flags=0):
+    return _check(_lib.gt_init(device, flags))
+
+
+def shutdown():
+    return _check(_lib.gt_shutdown())
+
+
+def version():
+    return _lib.gt_version().decode()
+
+
+# ---- the four calls ----
+
+def conv2d_run(problem, cfg, inp, filt, out, clk=None, stream=None):
+    _check(_lib.conv2d_run(ctypes.byref(problem), ctypes.byref(as_config(cfg)), clk or clock(),
+                           _ptr(inp), _ptr(filt), _ptr(out), _stream(stream)))
+
+
+def tune_space_enumerate(problem, values, max_threads=0, lds_limit=0, dedup_direct=True):
+    """values: dict name -> list of ints for the six tunables."""
+    arrs = [(ctypes.c_int32 * len(values[n]))(*values[n]) for n in CONFIG_FIELDS]
+    d = SpaceDesc()
+    for k, a in enumerate(arrs):
+        d.values[k] = ctypes.cast(a, ctypes.POINTER(ctypes.c_int32))
+        d.counts[k] = len(a)
+    d.flags = SPACE_DEDUP_DIRECT if dedup_direct else 0
+    d.max_threads = max_threads
+    d.lds_limit_bytes = lds_limit
+    n = ctypes.c_size_t(0)
+    rc = _lib.tune_space_enumerate(ctypes.byref(problem), ctypes.byref(d), None, 0, ctypes.byref(n))
+    if rc not in (GT_OK, GT_E_CAPACITY):
+        _check(rc)
+    out = (ConvConfig * max(n.value, 1))()
+    _check(_lib.tune_space_enumerate(ctypes.byref(problem), ctypes.byref(d), out, n.value, ctypes.byref(n)))
+    return [out[k] for k in range(n.value)]
+
+
+def measure_time_energy(problem, cfg, inp, filt, out, clk=None, window_s=1.0, discard_s=0.3,
+                        sample_period_ms=1.0, min_launches=10, warmup_launches=3, stream=None):
+    o = MeasureOpts(window_s, discard_s, sample_period_ms, min_launches, warmup_launches)
+    m = Measurement()
+    _check(_lib.measure_time_energy(ctypes.byref(problem), ctypes.byref(as_config(cfg)), clk or clock(),
+                                    ctypes.byref(o), _ptr(inp), _ptr(filt), _ptr(out), _stream(stream),
+                                    ctypes.byref(m)))
+    return m.as_dict()
+
+
+def fit_power_model(f_mhz, p_w, p_max, v=None, literal=False):
+    fa, n = _darr(f_mhz)
+    pa, n2 = _darr(p_w)
+    if n != n2:
+        raise ValueError("f and p differ in length")
+    va = _darr(v)[0] if v is not None else None
+    m = PowerModel()
+    m.literal_eq3 = 1 if literal else 0
+    _check(_lib.fit_power_model(fa, pa, va, n, float(p_max), ctypes.byref(m)))
+    return m
+
+
+def power_model_eval(model, f_mhz):
+    return _lib.gt_power_model_eval(ctypes.byref(model), float(f_mhz))
+
+
+def power_model_band(model, settable, rel_half=0.1):
+    sa, n = _darr(settable)
+    f_opt = ctypes.c_double(0)
+    band = (ctypes.c_double * max(n, 1))()
+    nb = ctypes.c_size_t(0)
+    _check(_lib.gt_power_model_band(ctypes.byref(model), sa, n, rel_half, ctypes.byref(f_opt), band, n,
+                                    ctypes.byref(nb)))
+    return f_opt.value, [band[k] for k in range(nb.value)]
+
+
+def energy_from_samples(t_s, p_w, t_start, t_stop, n_runs, discard_s):
+    ta, n = _darr(t_s)
+    pa, _ = _darr(p_w)
+    e, pm, nu = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_size_t(0)
+    _check(_lib.gt_energy_from_samples(ta, pa, n, t_start, t_stop, int(n_runs), discard_s,
+                                       ctypes.byref(e), ctypes.byref(pm), ctypes.byref(nu)))
+    return e.value, pm.value, nu.value
+
+
+def select(records, objective):
+    """records: list of dicts with t_run_s and e_run_j; objective 'time' | 'energy'."""
+    arr = (Measurement * len(records))()
+    for k, r in enumerate(records):
+        arr[k].t_run_s = r["t_run_s"]
+        arr[k].e_run_j = r["e_run_j"]
+    idx = ctypes.c_size_t(0)
+    _check(_lib.gt_select(arr, len(records), {"time": 0, "energy": 1}[objective], ctypes.byref(idx)))
+    return idx.value
+
+
+def problem_flops(problem):
+    return _lib.gt_problem_flops(ctypes.byref(problem))
+
+
+def lds_bytes(problem, cfg):
+    b = ctypes.c_int64(0)
+    _check(_lib.gt_conv_lds_bytes(ctypes.byref(problem), ctypes.byref(as_config(cfg)), ctypes.byref(b)))
+    return b.value
+
+
+def sensor_read():
+    s = SensorSample()
+    _check(_lib.gt_sensor_read(ctypes.byref(s)))
+    return s.as_dict()
+
+
+def settable_clocks(step_mhz=25.0):
+    n = ctypes.c_size_t(0)
+    rc = _lib.gt_settable_clocks(step_mhz, None, 0, ctypes.byref(n))
+    if rc not in (GT_OK, GT_E_CAPACITY):
+        _check(rc)
+    arr = (ctypes.c_double * max(n.value, 1))()
+    _check(_lib.gt_settable_clocks(step_mhz, arr, n.value, ctypes.byref(n)))
+    return [arr[k] for k in range(n.value)]
+
+
+def dvfs_state():
+    c = Clock()
+    active = _lib.gt_dvfs_state(ctypes.byref(c))
+    return bool(active), (c.kind, c.value)
+
+
+def fake_sensor_model(model, noise_w=0.0, seed=0):
+    _check(_lib.gt_fake_sensor_model(ctypes.byref(model), float(noise_w), int(seed)))
+
+
+def power_model(p_idle, alpha, beta, tau_mhz, p_max, literal=False):
+    m = PowerModel()
+    m.p_idle, m.alpha, m.beta, m.tau_mhz, m.p_max = p_idle, alpha, beta, tau_mhz, p_max
+    m.literal_eq3 = 1 if literal else 0
+    return m

@@ -1,0 +1,158 @@
+// measure_time_energy: the observer of sections III.A-III.B.
+//
+// The kernel is launched back-to-back for a window (1 s by default) while a
+// sampler thread polls the power sensor.  Time per launch comes from HIP
+// events around the window; energy per launch is the median power of the
+// samples taken after the stabilisation discard times that time (the paper's
+// E = <P> (t1 - t0) with the median for <P>).  The energy accumulator gives an
+// independent average power over the same kept interval, reported as
+// e_run_counter_j.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <thread>
+
+#include "gt_internal.hpp"
+
+using namespace gt;
+
+namespace {
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+}  // namespace
+
+extern "C" int measure_time_energy(const gt_problem *problem, const gt_conv_config *config,
+                                   gt_clock clock, const gt_measure_opts *opts, const void *d_in,
+                                   const void *d_filt, void *d_out, void *hip_stream,
+                                   gt_measurement *rec) {
+    clear_error();
+    if (!problem || !config || !d_in || !d_filt || !d_out || !rec)
+        return set_error(GT_E_INVAL, "measure_time_energy: null argument");
+    if (!state().inited) return set_error(GT_E_STATE, "measure_time_energy: call gt_init first");
+    if (state().flags & GT_INIT_HOST_ONLY)
+        return set_error(GT_E_STATE, "measure_time_energy: library initialised host-only");
+    gt_measure_opts o = opts ? *opts : gt_measure_opts{0, -1, 0, 0, -1};
+    if (!(o.window_s > 0)) o.window_s = 1.0;
+    if (o.discard_s < 0) o.discard_s = 0.3;
+    if (!(o.sample_period_ms > 0)) o.sample_period_ms = 1.0;
+    if (o.min_launches <= 0) o.min_launches = 10;
+    if (o.warmup_launches < 0) o.warmup_launches = 3;
+    if (o.discard_s >= o.window_s)
+        return set_error(GT_E_INVAL, "measure_time_energy: discard %.3f s >= window %.3f s",
+                         o.discard_s, o.window_s);
+    int rc = validate_problem_config(*problem, *config);
+    if (rc) return rc;
+    rc = dvfs_apply(clock);
+    if (rc) return rc;
+    rc = sensor_open();
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+
+    for (int k = 0; k < o.warmup_launches; ++k) {
+        rc = launch_problem(*problem, *config, d_in, d_filt, d_out, s);
+        if (rc) return rc;
+    }
+    EventPair est, win;
+    GT_HIP_CHECK(hipEventCreate(&est.a));
+    GT_HIP_CHECK(hipEventCreate(&est.b));
+    GT_HIP_CHECK(hipEventCreate(&win.a));
+    GT_HIP_CHECK(hipEventCreate(&win.b));
+    GT_HIP_CHECK(hipEventRecord(est.a, s));
+    for (int k = 0; k < 3; ++k) {
+        rc = launch_problem(*problem, *config, d_in, d_filt, d_out, s);
+        if (rc) return rc;
+    }
+    GT_HIP_CHECK(hipEventRecord(est.b, s));
+    GT_HIP_CHECK(hipEventSynchronize(est.b));
+    float est_ms = 0;
+    GT_HIP_CHECK(hipEventElapsedTime(&est_ms, est.a, est.b));
+    const double t_est = std::max(1e-7, est_ms * 1e-3 / 3.0);
+    const int64_t n = std::max<int64_t>(o.min_launches, (int64_t)std::ceil(o.window_s / t_est));
+
+    std::vector<gt_sensor_sample> samples;
+    samples.reserve((size_t)(o.window_s * 1000.0 / o.sample_period_ms) + 64);
+    std::atomic<bool> stop{false};
+    std::atomic<int> sensor_err{0};
+    sensor_set_busy(true);
+    std::thread sampler([&]() {
+        const auto period = std::chrono::duration<double>(o.sample_period_ms * 1e-3);
+        while (!stop.load()) {
+            gt_sensor_sample smp;
+            if (sensor_read(&smp) == GT_OK)
+                samples.push_back(smp);
+            else
+                sensor_err.store(1);
+            std::this_thread::sleep_for(period);
+        }
+    });
+    const double t_start = now_s();
+    hipError_t herr = hipEventRecord(win.a, s);
+    int64_t launched = 0;
+    for (; launched < n && herr == hipSuccess; ++launched) {
+        rc = launch_problem(*problem, *config, d_in, d_filt, d_out, s);
+        if (rc) break;
+    }
+    if (herr == hipSuccess && rc == GT_OK) herr = hipEventRecord(win.b, s);
+    if (herr == hipSuccess && rc == GT_OK) herr = hipEventSynchronize(win.b);
+    const double t_stop = now_s();
+    stop.store(true);
+    sampler.join();
+    sensor_set_busy(false);
+    if (rc) return rc;
+    if (herr != hipSuccess) return set_error(GT_E_HIP, "measure window: %s", hipGetErrorString(herr));
+    float win_ms = 0;
+    GT_HIP_CHECK(hipEventElapsedTime(&win_ms, win.a, win.b));
+
+    // keep the samples after the stabilisation discard
+    std::vector<double> kept_p;
+    double sclk_sum = 0;
+    int sclk_n = 0;
+    const gt_sensor_sample *first = nullptr, *last = nullptr;
+    for (const gt_sensor_sample &smp : samples) {
+        if (smp.t_s < t_start + o.discard_s || smp.t_s > t_stop) continue;
+        if (!std::isfinite(smp.power_w)) continue;
+        kept_p.push_back(smp.power_w);
+        if (std::isfinite(smp.sclk_mhz)) {
+            sclk_sum += smp.sclk_mhz;
+            ++sclk_n;
+        }
+        if (!first) first = &smp;
+        last = &smp;
+    }
+    if (kept_p.empty())
+        return set_error(GT_E_SENSOR, "measure_time_energy: no power sample in the kept window "
+                                      "(%zu samples, sensor errors %d)", samples.size(), sensor_err.load());
+    gt_measurement &m = *rec;
+    m = gt_measurement();
+    m.launches = launched;
+    m.window_s = win_ms * 1e-3;
+    m.t_run_s = m.window_s / (double)launched;
+    m.n_samples = (int64_t)samples.size();
+    m.n_used = (int64_t)kept_p.size();
+    m.p_median_w = median_of(kept_p);
+    m.p_min_w = *std::min_element(kept_p.begin(), kept_p.end());
+    m.p_max_w = *std::max_element(kept_p.begin(), kept_p.end());
+    m.e_run_j = m.p_median_w * m.t_run_s;
+    m.e_run_counter_j = NAN;
+    if (first && last && last->t_s > first->t_s && last->energy_j > first->energy_j)
+        m.e_run_counter_j = (last->energy_j - first->energy_j) / (last->t_s - first->t_s) * m.t_run_s;
+    const double flops = gt_problem_flops(problem);
+    m.gflops = flops / m.t_run_s * 1e-9;
+    m.gflops_per_w = flops / m.e_run_j * 1e-9;
+    m.sclk_req_mhz = dvfs_requested_mhz();
+    m.sclk_act_mhz = sclk_n ? sclk_sum / sclk_n : NAN;
+    const gt_sensor_sample &tail = samples.back();
+    m.mclk_mhz = tail.mclk_mhz;
+    m.volt_v = tail.volt_v;
+    m.temp_c = tail.temp_c;
+    m.throttled = (m.sclk_req_mhz > 0 && sclk_n && m.sclk_act_mhz < 0.98 * m.sclk_req_mhz) ? 1 : 0;
+    m.flags = ((state().flags & GT_INIT_FAKE_SENSOR) ? 1 : 0) | ((state().flags & GT_INIT_FAKE_DVFS) ? 2 : 0);
+    return GT_OK;
+}

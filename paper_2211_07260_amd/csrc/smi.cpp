@@ -1,0 +1,310 @@
+// Power sensor and DVFS controller.
+//
+// The paper reads board power, energy, clocks, voltage and temperature
+// through the vendor management library and sets the graphics clock or the
+// power limit as tunables (sections III.B and III.C).  Here the same roles go
+// to amd-smi: one GPU-metrics read per sample gives socket power, the energy
+// accumulator, per-XCD graphics clocks, memory clock, graphics voltage and
+// hotspot temperature; the clock knob is the graphics-clock upper limit and
+// the power knob the socket power cap.  Both need privileges; without
+// GT_INIT_ALLOW_DVFS the library refuses to change them (GT_E_PERM).
+//
+// Fake backends (for tests that must not touch the hardware):
+//   GT_INIT_FAKE_DVFS    the knob is only recorded; settable clocks 500..2400 MHz
+//   GT_INIT_FAKE_SENSOR  power follows a gt_power_model at the current clock
+//                        plus seeded Gaussian noise; idle power between kernels
+#include <amd_smi/amdsmi.h>
+
+#include <atomic>
+#include <cmath>
+
+#include "gt_internal.hpp"
+
+namespace gt {
+namespace {
+
+struct Smi {
+    bool open = false;
+    amdsmi_processor_handle h = nullptr;
+    double energy_res_j = 15.259e-6;
+    // restore state for DVFS
+    bool clk_changed = false, cap_changed = false;
+    uint64_t orig_max_clk = 0, orig_cap_uw = 0;
+    uint64_t last_energy_raw = 0;
+    double energy_wrap_j = 0;
+};
+
+struct Fake {
+    gt_power_model model{};
+    bool have_model = false;
+    double noise_w = 0;
+    uint64_t rng = 0x9E3779B97F4A7C15ull;
+    double e_j = 0, last_t = -1, last_p = 0;
+};
+
+Smi g_smi;
+Fake g_fake;
+std::mutex g_mu;
+std::atomic<bool> g_busy{false};
+
+const char *smi_str(amdsmi_status_t s) {
+    const char *str = nullptr;
+    if (amdsmi_status_code_to_string(s, &str) == AMDSMI_STATUS_SUCCESS && str) return str;
+    return "unknown amd-smi status";
+}
+
+int smi_open_locked() {
+    if (g_smi.open) return GT_OK;
+    const State &st = state();
+    if (st.flags & GT_INIT_HOST_ONLY) return set_error(GT_E_STATE, "sensor: host-only mode");
+    amdsmi_status_t s = amdsmi_init(AMDSMI_INIT_AMD_GPUS);
+    if (s != AMDSMI_STATUS_SUCCESS) return set_error(GT_E_SENSOR, "amdsmi_init: %s", smi_str(s));
+    uint32_t ns = 0;
+    s = amdsmi_get_socket_handles(&ns, nullptr);
+    if (s != AMDSMI_STATUS_SUCCESS || ns == 0)
+        return set_error(GT_E_SENSOR, "amd-smi: no sockets (%s)", smi_str(s));
+    std::vector<amdsmi_socket_handle> socks(ns);
+    amdsmi_get_socket_handles(&ns, socks.data());
+    for (uint32_t i = 0; i < ns && !g_smi.open; ++i) {
+        uint32_t np = 0;
+        if (amdsmi_get_processor_handles(socks[i], &np, nullptr) != AMDSMI_STATUS_SUCCESS) continue;
+        std::vector<amdsmi_processor_handle> procs(np);
+        amdsmi_get_processor_handles(socks[i], &np, procs.data());
+        for (uint32_t j = 0; j < np; ++j) {
+            amdsmi_bdf_t bdf;
+            if (amdsmi_get_gpu_device_bdf(procs[j], &bdf) != AMDSMI_STATUS_SUCCESS) continue;
+            if ((int)bdf.bus_number == st.dev.pci_bus && (int)bdf.device_number == st.dev.pci_device &&
+                (int)bdf.domain_number == st.dev.pci_domain) {
+                g_smi.h = procs[j];
+                g_smi.open = true;
+                break;
+            }
+        }
+    }
+    if (!g_smi.open)
+        return set_error(GT_E_SENSOR, "amd-smi: no processor matches PCI %04x:%02x:%02x",
+                         st.dev.pci_domain, st.dev.pci_bus, st.dev.pci_device);
+    uint64_t acc = 0, ts = 0;
+    float res = 0;
+    if (amdsmi_get_energy_count(g_smi.h, &acc, &res, &ts) == AMDSMI_STATUS_SUCCESS && res > 0)
+        g_smi.energy_res_j = res * 1e-6;
+    return GT_OK;
+}
+
+double gauss(uint64_t &state) {
+    auto next = [&state]() {
+        uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    const double u1 = ((next() >> 11) + 1.0) * (1.0 / 9007199254740993.0);
+    const double u2 = (next() >> 11) * (1.0 / 9007199254740992.0);
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+}
+
+constexpr double kFakeDefaultMhz = 2400.0;
+
+}  // namespace
+
+int sensor_open() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (state().flags & GT_INIT_FAKE_SENSOR) {
+        if (!g_fake.have_model) return set_error(GT_E_SENSOR, "fake sensor: call gt_fake_sensor_model");
+        return GT_OK;
+    }
+    return smi_open_locked();
+}
+
+void sensor_close() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_smi.open) {
+        amdsmi_shut_down();
+        g_smi = Smi();
+    }
+    g_fake.e_j = 0;
+    g_fake.last_t = -1;
+}
+
+void sensor_set_busy(bool busy) { g_busy.store(busy); }
+
+int sensor_read(gt_sensor_sample *out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    const State &st = state();
+    out->t_s = now_s();
+    if (st.flags & GT_INIT_FAKE_SENSOR) {
+        if (!g_fake.have_model) return set_error(GT_E_SENSOR, "fake sensor: no model");
+        double f = st.clock.kind == GT_CLOCK_SCLK_MHZ ? st.clock.value : kFakeDefaultMhz;
+        double p = g_busy.load() ? gt_power_model_eval(&g_fake.model, f) : g_fake.model.p_idle;
+        if (st.clock.kind == GT_CLOCK_POWER_CAP_W) p = std::min(p, (double)st.clock.value);
+        p += g_fake.noise_w * gauss(g_fake.rng);
+        if (g_fake.last_t >= 0) g_fake.e_j += g_fake.last_p * (out->t_s - g_fake.last_t);
+        g_fake.last_t = out->t_s;
+        g_fake.last_p = p;
+        out->power_w = p;
+        out->energy_j = g_fake.e_j;
+        out->sclk_mhz = f;
+        out->mclk_mhz = NAN;
+        out->volt_v = NAN;
+        out->temp_c = NAN;
+        return GT_OK;
+    }
+    int rc = smi_open_locked();
+    if (rc) return rc;
+    amdsmi_gpu_metrics_t m;
+    amdsmi_status_t s = amdsmi_get_gpu_metrics_info(g_smi.h, &m);
+    if (s != AMDSMI_STATUS_SUCCESS) return set_error(GT_E_SENSOR, "gpu metrics: %s", smi_str(s));
+    const uint16_t NA16 = 0xFFFF;
+    out->power_w = m.current_socket_power != NA16 ? (double)m.current_socket_power
+                                                  : (m.average_socket_power != NA16 ? (double)m.average_socket_power : NAN);
+    // energy accumulator: unwrap if it ever goes backwards
+    if (m.energy_accumulator < g_smi.last_energy_raw)
+        g_smi.energy_wrap_j += (double)g_smi.last_energy_raw * g_smi.energy_res_j;
+    g_smi.last_energy_raw = m.energy_accumulator;
+    out->energy_j = g_smi.energy_wrap_j + (double)m.energy_accumulator * g_smi.energy_res_j;
+    double sum = 0;
+    int cnt = 0;
+    for (int i = 0; i < AMDSMI_MAX_NUM_GFX_CLKS; ++i)
+        if (m.current_gfxclks[i] != NA16 && m.current_gfxclks[i] != 0) {
+            sum += m.current_gfxclks[i];
+            ++cnt;
+        }
+    out->sclk_mhz = cnt ? sum / cnt : (m.current_gfxclk != NA16 ? (double)m.current_gfxclk : NAN);
+    out->mclk_mhz = m.current_uclk != NA16 ? (double)m.current_uclk : NAN;
+    out->volt_v = (m.voltage_gfx != NA16 && m.voltage_gfx != 0) ? m.voltage_gfx * 1e-3 : NAN;
+    out->temp_c = m.temperature_hotspot != NA16 ? (double)m.temperature_hotspot : NAN;
+    return GT_OK;
+}
+
+double dvfs_requested_mhz() {
+    const gt_clock &c = state().clock;
+    return c.kind == GT_CLOCK_SCLK_MHZ ? (double)c.value : 0.0;
+}
+
+int dvfs_apply(const gt_clock &clk) {
+    State &st = state();
+    if (clk.kind == GT_CLOCK_DEFAULT) return GT_OK;  // never touches DVFS
+    if (clk.kind != GT_CLOCK_SCLK_MHZ && clk.kind != GT_CLOCK_POWER_CAP_W)
+        return set_error(GT_E_INVAL, "clock kind %d", clk.kind);
+    if (clk.value <= 0) return set_error(GT_E_INVAL, "clock value must be positive");
+    if (st.clock.kind == clk.kind && st.clock.value == clk.value) return GT_OK;
+    if (st.flags & GT_INIT_FAKE_DVFS) {
+        st.clock = clk;
+        return GT_OK;
+    }
+    if (!(st.flags & GT_INIT_ALLOW_DVFS))
+        return set_error(GT_E_PERM, "DVFS changes are not enabled (gt_init flag GT_INIT_ALLOW_DVFS)");
+    std::lock_guard<std::mutex> lk(g_mu);
+    int rc = smi_open_locked();
+    if (rc) return rc;
+    amdsmi_status_t s;
+    if (clk.kind == GT_CLOCK_SCLK_MHZ) {
+        if (!g_smi.clk_changed) {
+            amdsmi_clk_info_t ci;
+            if (amdsmi_get_clock_info(g_smi.h, AMDSMI_CLK_TYPE_GFX, &ci) == AMDSMI_STATUS_SUCCESS)
+                g_smi.orig_max_clk = ci.max_clk;
+        }
+        s = amdsmi_set_gpu_clk_limit(g_smi.h, AMDSMI_CLK_TYPE_GFX, CLK_LIMIT_MAX, (uint64_t)clk.value);
+        if (s == AMDSMI_STATUS_SUCCESS) g_smi.clk_changed = true;
+    } else {
+        if (!g_smi.cap_changed) {
+            amdsmi_power_cap_info_t pc;
+            if (amdsmi_get_power_cap_info(g_smi.h, 0, &pc) == AMDSMI_STATUS_SUCCESS)
+                g_smi.orig_cap_uw = pc.power_cap;
+        }
+        s = amdsmi_set_power_cap(g_smi.h, 0, (uint64_t)clk.value * 1000000ull);
+        if (s == AMDSMI_STATUS_SUCCESS) g_smi.cap_changed = true;
+    }
+    if (s == AMDSMI_STATUS_NO_PERM) return set_error(GT_E_PERM, "DVFS: permission denied");
+    if (s != AMDSMI_STATUS_SUCCESS) return set_error(GT_E_PERM, "DVFS: %s", smi_str(s));
+    st.clock = clk;
+    return GT_OK;
+}
+
+int dvfs_restore() {
+    State &st = state();
+    if (st.flags & GT_INIT_FAKE_DVFS) {
+        st.clock = gt_clock{GT_CLOCK_DEFAULT, 0};
+        return GT_OK;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    int rc = GT_OK;
+    if (g_smi.open && g_smi.clk_changed && g_smi.orig_max_clk) {
+        if (amdsmi_set_gpu_clk_limit(g_smi.h, AMDSMI_CLK_TYPE_GFX, CLK_LIMIT_MAX, g_smi.orig_max_clk) !=
+            AMDSMI_STATUS_SUCCESS)
+            rc = set_error(GT_E_PERM, "DVFS restore of the clock limit failed");
+        g_smi.clk_changed = false;
+    }
+    if (g_smi.open && g_smi.cap_changed && g_smi.orig_cap_uw) {
+        if (amdsmi_set_power_cap(g_smi.h, 0, g_smi.orig_cap_uw) != AMDSMI_STATUS_SUCCESS)
+            rc = set_error(GT_E_PERM, "DVFS restore of the power cap failed");
+        g_smi.cap_changed = false;
+    }
+    st.clock = gt_clock{GT_CLOCK_DEFAULT, 0};
+    return rc;
+}
+
+int dvfs_settable(double step_mhz, std::vector<double> &out) {
+    out.clear();
+    if (!(step_mhz > 0)) return set_error(GT_E_INVAL, "step must be positive");
+    double lo = 500, hi = 2400;
+    if (!(state().flags & GT_INIT_FAKE_DVFS)) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        int rc = smi_open_locked();
+        if (rc) return rc;
+        amdsmi_clk_info_t ci;
+        amdsmi_status_t s = amdsmi_get_clock_info(g_smi.h, AMDSMI_CLK_TYPE_GFX, &ci);
+        if (s != AMDSMI_STATUS_SUCCESS) return set_error(GT_E_SENSOR, "clock info: %s", smi_str(s));
+        lo = ci.min_clk;
+        hi = ci.max_clk;
+    }
+    for (double f = lo; f <= hi + 1e-9; f += step_mhz) out.push_back(f);
+    if (out.empty() || out.back() < hi) out.push_back(hi);
+    return GT_OK;
+}
+
+}  // namespace gt
+
+using namespace gt;
+
+extern "C" {
+
+int gt_sensor_read(gt_sensor_sample *s) {
+    clear_error();
+    if (!s) return set_error(GT_E_INVAL, "gt_sensor_read: null argument");
+    if (!state().inited) return set_error(GT_E_STATE, "gt_sensor_read: call gt_init first");
+    return sensor_read(s);
+}
+
+int gt_settable_clocks(double step_mhz, double *mhz, size_t cap, size_t *n) {
+    clear_error();
+    if (!n || (cap && !mhz)) return set_error(GT_E_INVAL, "gt_settable_clocks: null argument");
+    if (!state().inited) return set_error(GT_E_STATE, "gt_settable_clocks: call gt_init first");
+    std::vector<double> v;
+    int rc = dvfs_settable(step_mhz, v);
+    if (rc) return rc;
+    *n = v.size();
+    for (size_t i = 0; i < v.size() && i < cap; ++i) mhz[i] = v[i];
+    if (v.size() > cap) return set_error(GT_E_CAPACITY, "gt_settable_clocks: %zu clocks", v.size());
+    return GT_OK;
+}
+
+int gt_dvfs_state(gt_clock *current) {
+    clear_error();
+    if (!current) return set_error(GT_E_INVAL, "gt_dvfs_state: null argument");
+    *current = state().clock;
+    return current->kind != GT_CLOCK_DEFAULT ? 1 : 0;
+}
+
+int gt_fake_sensor_model(const gt_power_model *model, double noise_w, uint64_t seed) {
+    clear_error();
+    if (!model || noise_w < 0) return set_error(GT_E_INVAL, "gt_fake_sensor_model: bad argument");
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_fake.model = *model;
+    g_fake.have_model = true;
+    g_fake.noise_w = noise_w;
+    g_fake.rng = seed ^ 0x9E3779B97F4A7C15ull;
+    return GT_OK;
+}
+
+}  // extern "C"

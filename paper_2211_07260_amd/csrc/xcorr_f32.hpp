@@ -1,0 +1,220 @@
+// Tunable single-channel FP32 2-D cross-correlation for gfx950.
+//
+//   out[y][x] = sum_{i < fh} sum_{j < FW} in[y+i][x+j] * w[i][j]     (valid, no flip)
+//
+// Tunables (the section IV style: thread-block dimensions, work per thread,
+// shared-memory use, read path):
+//   blockDim.x/y       workgroup shape (runtime)
+//   TX, TY             outputs per thread along x / y (template)
+//   read path RP       0: the workgroup stages its input halo in LDS;
+//                      1: each thread reads global memory (L1/L2) directly
+//   LDS padding        runtime row pitch = ceil4(bx*TX + FW - 1) + 4*pad floats
+//
+// Every thread owns a TY x TX register tile of contiguous outputs.  For each
+// filter row i and each of its TY output rows it loads one input row segment
+// of TX + FW - 1 floats into registers and issues TX * FW FMAs against the
+// filter row, which is wave-uniform and therefore sits in SGPRs (scalar
+// loads), so each FMA is v_fmac_f32 acc, s_w, v_in.  Each output's sum is
+// accumulated in one FP32 chain in (i, j) order, so every configuration
+// produces bit-identical results.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gt {
+
+// Largest vector width (1, 2 or 4 floats) usable for LDS row reads that start
+// at a multiple of TX floats inside a 16-byte aligned row.
+template <int TX>
+struct RowVec {
+    static constexpr int value = (TX % 4 == 0) ? 4 : ((TX % 2 == 0) ? 2 : 1);
+};
+
+template <int V> struct VecT;
+template <> struct VecT<1> { typedef float type; };
+template <> struct VecT<2> { typedef float2 type; };
+template <> struct VecT<4> { typedef float4 type; };
+
+template <int N, int V>
+__device__ __forceinline__ void load_row_lds(float (&row)[N], const float *src) {
+    typedef typename VecT<V>::type vt;
+    constexpr int NV = N / V;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        vt v = reinterpret_cast<const vt *>(src)[k];
+        const float *pv = reinterpret_cast<const float *>(&v);
+#pragma unroll
+        for (int e = 0; e < V; ++e) row[k * V + e] = pv[e];
+    }
+#pragma unroll
+    for (int k = NV * V; k < N; ++k) row[k] = src[k];
+}
+
+// Global rows start at arbitrary float offsets; gfx950 global loads accept
+// dword alignment, so use 16-byte loads through memcpy (align 4).
+template <int N>
+__device__ __forceinline__ void load_row_global(float (&row)[N], const float *src) {
+    constexpr int NV = N / 4;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        float4 v;
+        __builtin_memcpy(&v, src + 4 * k, sizeof(float4));
+        row[4 * k + 0] = v.x;
+        row[4 * k + 1] = v.y;
+        row[4 * k + 2] = v.z;
+        row[4 * k + 3] = v.w;
+    }
+#pragma unroll
+    for (int k = NV * 4; k < N; ++k) row[k] = src[k];
+}
+
+template <int TX, int TY, int FW>
+__device__ __forceinline__ void fma_row(float (&acc)[TY][TX], int r, const float (&row)[TX + FW - 1],
+                                        const float (&wr)[FW]) {
+#pragma unroll
+    for (int j = 0; j < FW; ++j)
+#pragma unroll
+        for (int c = 0; c < TX; ++c) acc[r][c] = __builtin_fmaf(row[c + j], wr[j], acc[r][c]);
+}
+
+struct XcorrArgs {
+    const float *in;
+    const float *w;
+    float *out;
+    int32_t out_h, out_w, in_h, in_w, fh;
+    int32_t lds_pitch;  // floats (read path 0)
+    int32_t vec_ok;     // input base pointer is 16-byte aligned
+};
+
+template <int TX, int TY, int FW, int RP>
+__global__ __launch_bounds__(1024) void xcorr_f32_kernel(XcorrArgs a) {
+    constexpr int RW = TX + FW - 1;  // input row segment per thread
+    const int bx = blockDim.x, by = blockDim.y;
+    const int lx = threadIdx.x * TX, ly = threadIdx.y * TY;
+    const int x0 = blockIdx.x * bx * TX, y0 = blockIdx.y * by * TY;
+    const int fh = a.fh;
+    const float *__restrict__ w = a.w;
+
+    float acc[TY][TX];
+#pragma unroll
+    for (int r = 0; r < TY; ++r)
+#pragma unroll
+        for (int c = 0; c < TX; ++c) acc[r][c] = 0.0f;
+
+    if constexpr (RP == 0) {
+        extern __shared__ __align__(16) float lds[];
+        const int pitch = a.lds_pitch;
+        const int tile_w = bx * TX + FW - 1;
+        const int tile_h = by * TY + fh - 1;
+        const float *__restrict__ in = a.in;
+        // Stage the halo; rows and columns past the input are clamped (their
+        // outputs are never stored).  16-byte loads when rows are aligned.
+        const bool vec = a.vec_ok && ((a.in_w & 3) == 0) && ((x0 & 3) == 0);
+        const int tid_x = threadIdx.x, tid_y = threadIdx.y;
+        if (vec) {
+            const int tw4 = (tile_w + 3) >> 2;
+            for (int r = tid_y; r < tile_h; r += by) {
+                const int gy = min(y0 + r, a.in_h - 1);
+                const float *src = in + (size_t)gy * a.in_w;
+                float *dst = lds + r * pitch;
+                for (int c4 = tid_x; c4 < tw4; c4 += bx) {
+                    const int gx = x0 + 4 * c4;
+                    float4 v;
+                    if (gx + 3 < a.in_w) {
+                        v = *reinterpret_cast<const float4 *>(src + gx);
+                    } else {
+                        v.x = src[min(gx + 0, a.in_w - 1)];
+                        v.y = src[min(gx + 1, a.in_w - 1)];
+                        v.z = src[min(gx + 2, a.in_w - 1)];
+                        v.w = src[min(gx + 3, a.in_w - 1)];
+                    }
+                    *reinterpret_cast<float4 *>(dst + 4 * c4) = v;
+                }
+            }
+        } else {
+            for (int r = tid_y; r < tile_h; r += by) {
+                const int gy = min(y0 + r, a.in_h - 1);
+                const float *src = in + (size_t)gy * a.in_w;
+                float *dst = lds + r * pitch;
+                for (int c = tid_x; c < tile_w; c += bx) dst[c] = src[min(x0 + c, a.in_w - 1)];
+            }
+        }
+        __syncthreads();
+
+        constexpr int V = RowVec<TX>::value;
+        const float *base = lds + ly * pitch + lx;
+        for (int i = 0; i < fh; ++i) {
+            float wr[FW];
+#pragma unroll
+            for (int j = 0; j < FW; ++j) wr[j] = w[i * FW + j];
+#pragma unroll
+            for (int r = 0; r < TY; ++r) {
+                float row[RW];
+                load_row_lds<RW, V>(row, base + (r + i) * pitch);
+                fma_row<TX, TY, FW>(acc, r, row, wr);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < TY; ++r) {
+            const int y = y0 + ly + r;
+            if (y < a.out_h) {
+                float *dst = a.out + (size_t)y * a.out_w;
+#pragma unroll
+                for (int c = 0; c < TX; ++c) {
+                    const int x = x0 + lx + c;
+                    if (x < a.out_w) dst[x] = acc[r][c];
+                }
+            }
+        }
+    } else {
+        // Direct read path.  A thread whose tile hangs over the right or
+        // bottom edge computes the tile shifted back inside the output (same
+        // sums, in-bounds reads) and stores only its own outputs.
+        const int xt = x0 + lx, yt = y0 + ly;
+        const int xs = min(xt, a.out_w - TX), ys = min(yt, a.out_h - TY);
+        const float *base = a.in + (size_t)ys * a.in_w + xs;
+        for (int i = 0; i < fh; ++i) {
+            float wr[FW];
+#pragma unroll
+            for (int j = 0; j < FW; ++j) wr[j] = w[i * FW + j];
+#pragma unroll
+            for (int r = 0; r < TY; ++r) {
+                float row[RW];
+                load_row_global<RW>(row, base + (size_t)(r + i) * a.in_w);
+                fma_row<TX, TY, FW>(acc, r, row, wr);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < TY; ++r) {
+            const int y = ys + r;
+            if (y >= yt) {
+                float *dst = a.out + (size_t)y * a.out_w;
+#pragma unroll
+                for (int c = 0; c < TX; ++c) {
+                    const int x = xs + c;
+                    if (x >= xt) dst[x] = acc[r][c];
+                }
+            }
+        }
+    }
+}
+
+struct XcorrEntry {
+    int32_t tx, ty, fw, rp;
+    const void *fn;
+};
+
+}  // namespace gt
+
+// One translation unit per TX value instantiates TY 1..8 x FW x read path.
+#define GT_XCORR_ENTRIES_FW(TX, TY, FW) \
+    {TX, TY, FW, 0, (const void *)&gt::xcorr_f32_kernel<TX, TY, FW, 0>}, \
+    {TX, TY, FW, 1, (const void *)&gt::xcorr_f32_kernel<TX, TY, FW, 1>},
+#define GT_XCORR_ENTRIES_TY(TX, TY) \
+    GT_XCORR_ENTRIES_FW(TX, TY, 3) GT_XCORR_ENTRIES_FW(TX, TY, 5) \
+    GT_XCORR_ENTRIES_FW(TX, TY, 9) GT_XCORR_ENTRIES_FW(TX, TY, 17)
+#define GT_XCORR_TABLE(TX)                                                                      \
+    extern "C++" const gt::XcorrEntry gt_xcorr_table_tx##TX[] = {                               \
+        GT_XCORR_ENTRIES_TY(TX, 1) GT_XCORR_ENTRIES_TY(TX, 2) GT_XCORR_ENTRIES_TY(TX, 3)        \
+        GT_XCORR_ENTRIES_TY(TX, 4) GT_XCORR_ENTRIES_TY(TX, 5) GT_XCORR_ENTRIES_TY(TX, 6)        \
+        GT_XCORR_ENTRIES_TY(TX, 7) GT_XCORR_ENTRIES_TY(TX, 8) {0, 0, 0, 0, nullptr}};

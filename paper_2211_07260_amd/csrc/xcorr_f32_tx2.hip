@@ -1,0 +1,3 @@
+// Instantiations of the FP32 cross-correlation kernel for tile_size_x = 2.
+#include "xcorr_f32.hpp"
+GT_XCORR_TABLE(2)

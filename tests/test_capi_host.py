@@ -1,0 +1,221 @@
+"""Host-side C-ABI tests (no GPU): the library loads, exports every symbol the
+header declares, and its host arithmetic agrees with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2211_07260_amd as gt
+from oracle import measure as om
+from oracle import power_model as opm
+from oracle import space as osp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    names = []
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if not h.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                             src, flags=re.M):
+            names.append(m.group(1))
+    return sorted(set(names))
+
+
+def test_header_symbols_exported():
+    names = header_functions()
+    assert {"conv2d_run", "tune_space_enumerate", "measure_time_energy", "fit_power_model"} <= set(names)
+    lib = gt.lib()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) == set(gt.EXPORTED)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def host_only():
+    gt.init(0, gt.INIT_HOST_ONLY)
+    yield
+    gt.shutdown()
+
+
+def test_gpu_calls_refused_host_only():
+    import torch
+    t = torch.zeros(4)
+    with pytest.raises(gt.GreentuneError) as e:
+        gt.conv2d_run(gt.xcorr_problem(2, 2, 3, 3), gt.config(), t, t, t, stream=0)
+    assert e.value.code == gt.GT_E_STATE
+
+
+VALUES = dict(block_size_x=[16, 32, 64, 128], block_size_y=[1, 2, 4, 8, 16],
+              tile_size_x=list(range(1, 9)), tile_size_y=list(range(1, 9)),
+              use_lds_padding=[0, 1], read_path=[0])
+
+
+@pytest.mark.parametrize("lds", [65536, 163840])
+@pytest.mark.parametrize("f", [3, 17])
+def test_enumerate_matches_oracle(lds, f):
+    p = gt.xcorr_problem(4096, 4096, f, f)
+    got = [c.as_tuple() for c in gt.tune_space_enumerate(p, VALUES, max_threads=1024, lds_limit=lds)]
+    want = osp.enumerate_space(VALUES, f, f, max_threads=1024, lds_limit=lds)
+    assert got == want
+
+
+def test_enumerate_with_read_path_and_dedup():
+    p = gt.xcorr_problem(4096, 4096, 17, 17)
+    vals = dict(VALUES, read_path=[0, 1])
+    got = [c.as_tuple() for c in gt.tune_space_enumerate(p, vals, max_threads=1024, lds_limit=163840)]
+    want = osp.enumerate_space(vals, 17, 17, max_threads=1024, lds_limit=163840)
+    assert got == want
+    got2 = gt.tune_space_enumerate(p, vals, max_threads=1024, lds_limit=163840, dedup_direct=False)
+    assert len(got2) == len(osp.enumerate_space(vals, 17, 17, 1024, 163840, dedup_direct=False))
+
+
+def test_enumerate_counts_documented():
+    p = gt.xcorr_problem(4096, 4096, 17, 17)
+    assert len(gt.tune_space_enumerate(p, VALUES, max_threads=1024, lds_limit=1 << 40)) == 2432
+
+
+def test_enumerate_capacity_error():
+    import ctypes
+    p = gt.xcorr_problem(64, 64, 3, 3)
+    arrs = [(ctypes.c_int32 * len(VALUES[n]))(*VALUES[n]) for n in gt.CONFIG_FIELDS]
+    d = gt.SpaceDesc()
+    for k, a in enumerate(arrs):
+        d.values[k] = ctypes.cast(a, ctypes.POINTER(ctypes.c_int32))
+        d.counts[k] = len(a)
+    d.max_threads, d.lds_limit_bytes = 1024, 65536
+    out = (gt.ConvConfig * 3)()
+    n = ctypes.c_size_t(0)
+    rc = gt.lib().tune_space_enumerate(ctypes.byref(p), ctypes.byref(d), out, 3, ctypes.byref(n))
+    assert rc == gt.GT_E_CAPACITY and n.value > 3
+
+
+def test_lds_bytes_matches_oracle():
+    p = gt.xcorr_problem(256, 256, 17, 17)
+    for c in [(32, 8, 4, 4, 0, 0), (16, 16, 3, 5, 1, 0), (128, 4, 8, 2, 1, 0)]:
+        assert gt.lds_bytes(p, c) == osp.lds_bytes(c[0], c[1], c[2], c[3], c[4], 17, 17)
+    assert gt.lds_bytes(p, (32, 8, 4, 4, 0, 1)) == 0
+
+
+def test_flops():
+    assert gt.problem_flops(gt.xcorr_problem(4096, 4096, 17, 17)) == om.flops_xcorr(4096, 4096, 17, 17)
+    p = gt.conv_problem(gt.IGEMM_BF16_MFMA, 16, 128, 128, 64, 64, 3, 3)
+    assert gt.problem_flops(p) == om.flops_conv(16, 128, 128, 64, 64, 3, 3)
+
+
+def test_energy_from_samples_matches_oracle():
+    rng = np.random.default_rng(1)
+    for n in (7, 8, 101):
+        t = np.sort(rng.uniform(0, 1.2, n))
+        p = rng.uniform(300, 900, n)
+        e, pm, nu = gt.energy_from_samples(t, p, 0.05, 1.1, 977, 0.3)
+        e2, pm2, t_run, nu2 = om.energy_per_run(t, p, 0.05, 1.1, 977, 0.3)
+        assert nu == nu2 and pm == pm2 and e == pytest.approx(e2, rel=1e-15)
+
+
+def test_energy_from_samples_empty_window():
+    with pytest.raises(gt.GreentuneError) as e:
+        gt.energy_from_samples([0.0, 0.1], [1.0, 2.0], 0.0, 1.0, 10, 0.5)
+    assert e.value.code == gt.GT_E_SENSOR
+
+
+def test_select_matches_oracle():
+    rng = np.random.default_rng(2)
+    for _ in range(20):
+        rows = [dict(t_run_s=float(rng.integers(1, 5)), e_run_j=float(rng.integers(1, 5))) for _ in range(12)]
+        orows = [dict(t_run=r["t_run_s"], e_run=r["e_run_j"]) for r in rows]
+        for obj in ("time", "energy"):
+            assert gt.select(rows, obj) == om.select(orows, obj)
+
+
+MODELS = [dict(p_idle=180.0, alpha=0.12, beta=0.0012, tau=1350.0, p_max=5000.0),
+          dict(p_idle=90.0, alpha=0.08, beta=0.0020, tau=1100.0, p_max=5000.0),
+          dict(p_idle=250.0, alpha=0.3, beta=0.0015, tau=1500.0, p_max=1000.0)]
+
+
+@pytest.mark.parametrize("m", MODELS)
+def test_eval_matches_oracle(m):
+    pmod = gt.power_model(m["p_idle"], m["alpha"], m["beta"], m["tau"], m["p_max"])
+    for f in np.linspace(300, 2500, 57):
+        want = float(opm.power(f, m["p_idle"], m["alpha"], m["beta"], m["tau"], m["p_max"]))
+        assert gt.power_model_eval(pmod, f) == pytest.approx(want, rel=1e-15)
+    lit = gt.power_model(m["p_idle"], m["alpha"], m["beta"], m["tau"], m["p_max"], literal=True)
+    for f in (m["tau"] - 1, m["tau"], m["tau"] + 300):
+        want = float(opm.power(f, m["p_idle"], m["alpha"], m["beta"], m["tau"], m["p_max"], literal=True))
+        assert gt.power_model_eval(lit, f) == pytest.approx(want, rel=1e-15)
+
+
+@pytest.mark.parametrize("m", MODELS + [dict(p_idle=0.0, alpha=0.5, beta=0.01, tau=1200.0, p_max=1e9),
+                                       dict(p_idle=300.0, alpha=0.1, beta=0.0, tau=1000.0, p_max=1e9)])
+@pytest.mark.parametrize("step", [100.0, 25.0, 5.0])
+def test_band_matches_oracle(m, step):
+    settable = list(np.arange(500.0, 2400.0 + 1e-9, step))
+    pmod = gt.power_model(m["p_idle"], m["alpha"], m["beta"], m["tau"], m["p_max"])
+    f_opt, band = gt.power_model_band(pmod, settable, 0.1)
+    om_ = dict(m)
+    assert f_opt == opm.optimal_clock(settable, om_)
+    assert band == opm.clock_band(settable, f_opt, 0.1)
+
+
+def _synth(f, m):
+    return opm.power(np.asarray(f), m["p_idle"], m["alpha"], m["beta"], m["tau"], m["p_max"])
+
+
+@pytest.mark.parametrize("m", MODELS[:2])
+def test_fit_recovers_noise_free(m):
+    f = np.linspace(500.0, 2400.0, 9)
+    r = gt.fit_power_model(f, _synth(f, m), m["p_max"])
+    assert r.rss < 1e-12
+    assert r.p_idle == pytest.approx(m["p_idle"], rel=1e-6)
+    assert r.alpha == pytest.approx(m["alpha"], rel=1e-6)
+    assert r.beta == pytest.approx(m["beta"], rel=1e-6)
+    assert r.tau_mhz == pytest.approx(m["tau"], rel=1e-6)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_fit_noisy_matches_oracle_sse(seed):
+    rng = np.random.default_rng(seed)
+    m = dict(p_idle=rng.uniform(100, 300), alpha=rng.uniform(0.05, 0.3), beta=rng.uniform(0.0005, 0.002),
+             tau=rng.uniform(900, 1700), p_max=1e9)
+    f = np.linspace(500.0, 2400.0, int(rng.integers(5, 10)))
+    p = _synth(f, m) + rng.normal(0, 4.0, f.size)
+    r = gt.fit_power_model(f, p, m["p_max"])
+    o = opm.fit(f, p, m["p_max"])
+    # the product's LM must reach the oracle's global least-squares minimum
+    assert r.rss <= o["sse"] * (1 + 1e-6) + 1e-9
+    # and report the SSE of the parameters it returns
+    assert r.rss == pytest.approx(opm.sse((r.p_idle, r.alpha, r.beta, r.tau_mhz), f, p, m["p_max"]), rel=1e-9)
+
+
+def test_fit_with_clipping():
+    m = dict(p_idle=200.0, alpha=0.2, beta=0.0015, tau=1200.0, p_max=900.0)
+    f = np.linspace(500.0, 2400.0, 11)
+    p = _synth(f, m)
+    r = gt.fit_power_model(f, p, m["p_max"])
+    o = opm.fit(f, p, m["p_max"])
+    assert r.rss <= o["sse"] * (1 + 1e-6) + 1e-9
+    assert r.rss < 1e-8
+
+
+def test_fit_measured_voltage():
+    f = np.array([600.0, 1000.0, 1400.0, 1800.0, 2200.0])
+    v = np.array([0.70, 0.70, 0.78, 0.90, 1.05])
+    p = 120.0 + 0.3 * f * v * v
+    r = gt.fit_power_model(f, p, 1e9, v=v)
+    o = opm.fit(f, p, 1e9, v=v)
+    assert r.v_measured == 1
+    assert r.p_idle == pytest.approx(o["p_idle"], rel=1e-8)
+    assert r.alpha == pytest.approx(o["alpha"], rel=1e-8)
+
+
+def test_fit_rejects_bad_input():
+    with pytest.raises(gt.GreentuneError):
+        gt.fit_power_model([1000, 2000, 1500], [100, 200, 150], 1000.0)  # too few for Eq. 3
+    with pytest.raises(gt.GreentuneError):
+        gt.fit_power_model([1000, -5, 1500, 1200], [100, 200, 150, 120], 1000.0)
