@@ -138,9 +138,10 @@ typedef struct {
 /* One sensor reading. */
 typedef struct {
     double t_s;               /* host steady clock, seconds */
-    double power_w;           /* current socket power */
+    double power_w;           /* socket power (hwmon power1_input, refreshed every few ms) */
     double energy_j;          /* energy accumulator (monotone, wraps are unwrapped) */
-    double sclk_mhz, mclk_mhz, volt_v, temp_c;
+    double energy_t_s;        /* firmware timestamp of that accumulator value, seconds */
+    double sclk_mhz, mclk_mhz, volt_v, temp_c;  /* from the GPU metrics table (about 1 Hz) */
 } gt_sensor_sample;
 
 /* ---- lifecycle ---- */
@@ -240,6 +241,16 @@ int gt_dvfs_state(gt_clock *current);
  * the given standard deviation (deterministic, seeded).  Idle power applies
  * when no kernel is running in the window. */
 int gt_fake_sensor_model(const gt_power_model *model, double noise_w, uint64_t seed);
+
+/* ---- roofline probes ---- */
+
+/* Measure the achievable FP32 vector FMA rate (FMA with one SGPR operand, the
+ * form the convolution issues; packed FP32 is not used) and the device copy
+ * bandwidth (read + write bytes), on hip_stream.  d_buf: caller-owned device
+ * scratch of `bytes` >= 4 MiB (overwritten).  Blocks until done.
+ * Errors: GT_E_INVAL (buffer), GT_E_STATE (no device), GT_E_HIP. */
+int gt_roofline_probe(void *d_buf, size_t bytes, void *hip_stream, double *fp32_fma_tflops,
+                      double *copy_gbs);
 
 #ifdef __cplusplus
 }

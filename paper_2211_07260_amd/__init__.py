@@ -84,8 +84,8 @@ class PowerModel(ctypes.Structure):
 
 
 class SensorSample(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_double) for n in ("t_s", "power_w", "energy_j", "sclk_mhz", "mclk_mhz",
-                                               "volt_v", "temp_c")]
+    _fields_ = [(n, ctypes.c_double) for n in ("t_s", "power_w", "energy_j", "energy_t_s", "sclk_mhz",
+                                               "mclk_mhz", "volt_v", "temp_c")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -134,6 +134,7 @@ def _load():
         "gt_settable_clocks": ([c_double, P(c_double), c_size, P(c_size)], c_int),
         "gt_dvfs_state": ([P(Clock)], c_int),
         "gt_fake_sensor_model": ([P(PowerModel), c_double, ctypes.c_uint64], c_int),
+        "gt_roofline_probe": ([vp, c_size, vp, P(c_double), P(c_double)], c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -147,7 +148,7 @@ EXPORTED = ("gt_init", "gt_shutdown", "gt_last_error", "gt_version", "conv2d_run
             "tune_space_enumerate", "measure_time_energy", "fit_power_model", "gt_power_model_eval",
             "gt_power_model_band", "gt_energy_from_samples", "gt_select", "gt_problem_flops",
             "gt_conv_lds_bytes", "gt_sensor_read", "gt_settable_clocks", "gt_dvfs_state",
-            "gt_fake_sensor_model")
+            "gt_fake_sensor_model", "gt_roofline_probe")
 
 
 def lib():
@@ -340,3 +341,12 @@ def power_model(p_idle, alpha, beta, tau_mhz, p_max, literal=False):
     m.p_idle, m.alpha, m.beta, m.tau_mhz, m.p_max = p_idle, alpha, beta, tau_mhz, p_max
     m.literal_eq3 = 1 if literal else 0
     return m
+
+
+def roofline_probe(buf, stream=None):
+    """Achievable FP32 FMA TFLOP/s and copy GB/s on this device (buf: device
+    tensor of >= 4 MiB, overwritten)."""
+    t, g = ctypes.c_double(0), ctypes.c_double(0)
+    _check(_lib.gt_roofline_probe(_ptr(buf), buf.numel() * buf.element_size(), _stream(stream),
+                                  ctypes.byref(t), ctypes.byref(g)))
+    return t.value, g.value

@@ -5,8 +5,8 @@
 // events around the window; energy per launch is the median power of the
 // samples taken after the stabilisation discard times that time (the paper's
 // E = <P> (t1 - t0) with the median for <P>).  The energy accumulator gives an
-// independent average power over the same kept interval, reported as
-// e_run_counter_j.
+// independent average power over an interval inside the kept window, reported
+// as e_run_counter_j.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -114,7 +114,6 @@ extern "C" int measure_time_energy(const gt_problem *problem, const gt_conv_conf
     std::vector<double> kept_p;
     double sclk_sum = 0;
     int sclk_n = 0;
-    const gt_sensor_sample *first = nullptr, *last = nullptr;
     for (const gt_sensor_sample &smp : samples) {
         if (smp.t_s < t_start + o.discard_s || smp.t_s > t_stop) continue;
         if (!std::isfinite(smp.power_w)) continue;
@@ -123,8 +122,6 @@ extern "C" int measure_time_energy(const gt_problem *problem, const gt_conv_conf
             sclk_sum += smp.sclk_mhz;
             ++sclk_n;
         }
-        if (!first) first = &smp;
-        last = &smp;
     }
     if (kept_p.empty())
         return set_error(GT_E_SENSOR, "measure_time_energy: no power sample in the kept window "
@@ -140,9 +137,23 @@ extern "C" int measure_time_energy(const gt_problem *problem, const gt_conv_conf
     m.p_min_w = *std::min_element(kept_p.begin(), kept_p.end());
     m.p_max_w = *std::max_element(kept_p.begin(), kept_p.end());
     m.e_run_j = m.p_median_w * m.t_run_s;
+    // Energy-counter cross-check: the accumulator updates about once per
+    // second with a firmware timestamp.  Use the first and last updates
+    // observed inside the kept interval; their timestamps bound an interval
+    // that lies wholly inside the window.  NaN when fewer than two updates.
     m.e_run_counter_j = NAN;
-    if (first && last && last->t_s > first->t_s && last->energy_j > first->energy_j)
-        m.e_run_counter_j = (last->energy_j - first->energy_j) / (last->t_s - first->t_s) * m.t_run_s;
+    {
+        const gt_sensor_sample *ua = nullptr, *ub = nullptr;
+        for (size_t k = 1; k < samples.size(); ++k) {
+            const gt_sensor_sample &a = samples[k - 1], &b = samples[k];
+            if (!(b.energy_t_s != a.energy_t_s) || !std::isfinite(b.energy_j)) continue;
+            if (a.t_s < t_start + o.discard_s || b.t_s > t_stop) continue;
+            if (!ua) ua = &b;
+            ub = &b;
+        }
+        if (ua && ub && ub->energy_t_s > ua->energy_t_s)
+            m.e_run_counter_j = (ub->energy_j - ua->energy_j) / (ub->energy_t_s - ua->energy_t_s) * m.t_run_s;
+    }
     const double flops = gt_problem_flops(problem);
     m.gflops = flops / m.t_run_s * 1e-9;
     m.gflops_per_w = flops / m.e_run_j * 1e-9;

@@ -1,0 +1,83 @@
+// Roofline probes: the achievable FP32 vector FMA rate (the same
+// v_fmac_f32 acc, s_w, v_in form the convolution issues, packed FP32
+// disabled) and the HBM copy bandwidth, measured on the device at hand.
+#include <hip/hip_runtime.h>
+
+#include "gt_internal.hpp"
+
+namespace gt {
+
+// 32 independent accumulators, 8 input registers, weights from SGPRs:
+// 256 FMAs per loop trip per lane.
+__global__ __launch_bounds__(256) void fma_peak_kernel(float *out, const float *w, int iters) {
+    float acc[32], x[8];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) acc[k] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = (float)(threadIdx.x + k) * 1e-3f;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float s = w[j];
+#pragma unroll
+            for (int k = 0; k < 32; ++k) acc[k] = __builtin_fmaf(x[(k + j) & 7], s, acc[k]);
+        }
+    }
+    float t = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) t += acc[k];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void copy_kernel(const float4 *__restrict__ src, float4 *__restrict__ dst,
+                                                   size_t n4) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) dst[i] = src[i];
+}
+
+}  // namespace gt
+
+using namespace gt;
+
+extern "C" int gt_roofline_probe(void *d_buf, size_t bytes, void *hip_stream, double *fp32_fma_tflops,
+                                 double *copy_gbs) {
+    clear_error();
+    if (!d_buf || !fp32_fma_tflops || !copy_gbs) return set_error(GT_E_INVAL, "gt_roofline_probe: null argument");
+    if (!state().inited || (state().flags & GT_INIT_HOST_ONLY))
+        return set_error(GT_E_STATE, "gt_roofline_probe: needs gt_init on a device");
+    const size_t half = (bytes / 2) / 16 * 16;
+    if (half < (1u << 20)) return set_error(GT_E_INVAL, "gt_roofline_probe: buffer must hold at least 2 MiB");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int cus = state().dev.cu_count > 0 ? state().dev.cu_count : 256;
+    const int blocks = cus * 8, iters = 2048;
+    if ((size_t)(blocks * 256 + 8) * sizeof(float) > bytes)
+        return set_error(GT_E_INVAL, "gt_roofline_probe: buffer too small");
+    float *out = static_cast<float *>(d_buf);
+    const float *w = out + blocks * 256;  // 8 filter-like values past the outputs (contents irrelevant)
+    hipEvent_t a, b;
+    GT_HIP_CHECK(hipEventCreate(&a));
+    GT_HIP_CHECK(hipEventCreate(&b));
+    hipLaunchKernelGGL(fma_peak_kernel, dim3(blocks), dim3(256), 0, s, out, w, iters);  // warm
+    GT_HIP_CHECK(hipEventRecord(a, s));
+    hipLaunchKernelGGL(fma_peak_kernel, dim3(blocks), dim3(256), 0, s, out, w, iters);
+    GT_HIP_CHECK(hipEventRecord(b, s));
+    GT_HIP_CHECK(hipEventSynchronize(b));
+    float ms = 0;
+    GT_HIP_CHECK(hipEventElapsedTime(&ms, a, b));
+    *fp32_fma_tflops = 2.0 * 256.0 * iters * (double)blocks * 256 / (ms * 1e-3) / 1e12;
+
+    const size_t n4 = half / 16;
+    const float4 *src = static_cast<const float4 *>(d_buf);
+    float4 *dst = reinterpret_cast<float4 *>(static_cast<char *>(d_buf) + half);
+    hipLaunchKernelGGL(copy_kernel, dim3(cus * 16), dim3(256), 0, s, src, dst, n4);
+    GT_HIP_CHECK(hipEventRecord(a, s));
+    const int reps = 10;
+    for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(copy_kernel, dim3(cus * 16), dim3(256), 0, s, src, dst, n4);
+    GT_HIP_CHECK(hipEventRecord(b, s));
+    GT_HIP_CHECK(hipEventSynchronize(b));
+    GT_HIP_CHECK(hipEventElapsedTime(&ms, a, b));
+    *copy_gbs = 2.0 * (double)n4 * 16 * reps / (ms * 1e-3) / 1e9;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return GT_OK;
+}

@@ -2,11 +2,16 @@
 //
 // The paper reads board power, energy, clocks, voltage and temperature
 // through the vendor management library and sets the graphics clock or the
-// power limit as tunables (sections III.B and III.C).  Here the same roles go
-// to amd-smi: one GPU-metrics read per sample gives socket power, the energy
-// accumulator, per-XCD graphics clocks, memory clock, graphics voltage and
-// hotspot temperature; the clock knob is the graphics-clock upper limit and
-// the power knob the socket power cap.  Both need privileges; without
+// power limit as tunables (sections III.B and III.C).  On MI355X the roles
+// split by refresh rate:
+//   - socket power comes from the amdgpu hwmon file power1_input (microwatts),
+//     which the firmware refreshes every few milliseconds;
+//   - the GPU metrics table read through amd-smi (energy accumulator with its
+//     firmware timestamp, per-XCD graphics clocks, memory clock, graphics
+//     voltage, hotspot temperature) refreshes about once per second, so it is
+//     re-read at most every 50 ms and serves as the slow cross-check.
+// The clock knob is the graphics-clock upper limit and the power knob the
+// socket power cap, both through amd-smi.  Both need privileges; without
 // GT_INIT_ALLOW_DVFS the library refuses to change them (GT_E_PERM).
 //
 // Fake backends (for tests that must not touch the hardware):
@@ -15,8 +20,17 @@
 //                        plus seeded Gaussian noise; idle power between kernels
 #include <amd_smi/amdsmi.h>
 
+#include <dirent.h>
+#include <stdio.h>
+#include <string.h>
+#include <fcntl.h>
+#include <limits.h>
+#include <stdlib.h>
+#include <unistd.h>
+
 #include <atomic>
 #include <cmath>
+#include <string>
 
 #include "gt_internal.hpp"
 
@@ -32,6 +46,9 @@ struct Smi {
     uint64_t orig_max_clk = 0, orig_cap_uw = 0;
     uint64_t last_energy_raw = 0;
     double energy_wrap_j = 0;
+    int hwmon_fd = -1;            // power1_input of this device
+    double metrics_t = -1;        // host time of the cached metrics read
+    gt_sensor_sample cached{};    // slow fields of the last metrics read
 };
 
 struct Fake {
@@ -51,6 +68,45 @@ const char *smi_str(amdsmi_status_t s) {
     const char *str = nullptr;
     if (amdsmi_status_code_to_string(s, &str) == AMDSMI_STATUS_SUCCESS && str) return str;
     return "unknown amd-smi status";
+}
+
+// Locate /sys/class/drm/cardN/device/hwmon/hwmonM/power1_input for the PCI
+// address of the HIP device; -1 if none.
+int open_hwmon_power(const DeviceInfo &d) {
+    DIR *drm = opendir("/sys/class/drm");
+    if (!drm) return -1;
+    int fd = -1;
+    while (struct dirent *e = readdir(drm)) {
+        if (strncmp(e->d_name, "card", 4) != 0 || strchr(e->d_name, '-')) continue;
+        std::string dev = std::string("/sys/class/drm/") + e->d_name + "/device";
+        char real[PATH_MAX];
+        if (!realpath(dev.c_str(), real)) continue;
+        const char *base = strrchr(real, '/');
+        unsigned dom = 0, bus = 0, slot = 0, fn = 0;
+        if (!base || sscanf(base + 1, "%x:%x:%x.%x", &dom, &bus, &slot, &fn) != 4) continue;
+        if ((int)dom != d.pci_domain || (int)bus != d.pci_bus || (int)slot != d.pci_device) continue;
+        DIR *hw = opendir((dev + "/hwmon").c_str());
+        if (!hw) continue;
+        while (struct dirent *h = readdir(hw)) {
+            if (strncmp(h->d_name, "hwmon", 5) != 0) continue;
+            fd = open((dev + "/hwmon/" + h->d_name + "/power1_input").c_str(), O_RDONLY | O_CLOEXEC);
+            if (fd >= 0) break;
+        }
+        closedir(hw);
+        if (fd >= 0) break;
+    }
+    closedir(drm);
+    return fd;
+}
+
+double read_hwmon_w(int fd) {
+    char buf[64];
+    const ssize_t n = pread(fd, buf, sizeof buf - 1, 0);
+    if (n <= 0) return NAN;
+    buf[n] = 0;
+    char *end = nullptr;
+    const double uw = strtod(buf, &end);
+    return end == buf ? NAN : uw * 1e-6;
 }
 
 int smi_open_locked() {
@@ -88,6 +144,44 @@ int smi_open_locked() {
     float res = 0;
     if (amdsmi_get_energy_count(g_smi.h, &acc, &res, &ts) == AMDSMI_STATUS_SUCCESS && res > 0)
         g_smi.energy_res_j = res * 1e-6;
+    g_smi.hwmon_fd = open_hwmon_power(st.dev);
+    g_smi.metrics_t = -1;
+    return GT_OK;
+}
+
+// Re-read the slow metrics (about 1 Hz upstream) at most every 50 ms.
+int refresh_metrics_locked(double now) {
+    if (g_smi.metrics_t >= 0 && now - g_smi.metrics_t < 0.05) return GT_OK;
+    amdsmi_gpu_metrics_t m;
+    amdsmi_status_t s = amdsmi_get_gpu_metrics_info(g_smi.h, &m);
+    if (s != AMDSMI_STATUS_SUCCESS) return set_error(GT_E_SENSOR, "gpu metrics: %s", smi_str(s));
+    gt_sensor_sample &c = g_smi.cached;
+    const uint16_t NA16 = 0xFFFF;
+    c.power_w = m.current_socket_power != NA16 ? (double)m.current_socket_power
+                                               : (m.average_socket_power != NA16 ? (double)m.average_socket_power : NAN);
+    uint64_t acc = 0, ts = 0;
+    float res = 0;
+    if (amdsmi_get_energy_count(g_smi.h, &acc, &res, &ts) == AMDSMI_STATUS_SUCCESS) {
+        if (acc < g_smi.last_energy_raw) g_smi.energy_wrap_j += (double)g_smi.last_energy_raw * g_smi.energy_res_j;
+        g_smi.last_energy_raw = acc;
+        c.energy_j = g_smi.energy_wrap_j + (double)acc * g_smi.energy_res_j;
+        c.energy_t_s = ts * 1e-9;
+    } else {
+        c.energy_j = NAN;
+        c.energy_t_s = NAN;
+    }
+    double sum = 0;
+    int cnt = 0;
+    for (int i = 0; i < AMDSMI_MAX_NUM_GFX_CLKS; ++i)
+        if (m.current_gfxclks[i] != NA16 && m.current_gfxclks[i] != 0) {
+            sum += m.current_gfxclks[i];
+            ++cnt;
+        }
+    c.sclk_mhz = cnt ? sum / cnt : (m.current_gfxclk != NA16 ? (double)m.current_gfxclk : NAN);
+    c.mclk_mhz = m.current_uclk != NA16 ? (double)m.current_uclk : NAN;
+    c.volt_v = (m.voltage_gfx != NA16 && m.voltage_gfx != 0) ? m.voltage_gfx * 1e-3 : NAN;
+    c.temp_c = m.temperature_hotspot != NA16 ? (double)m.temperature_hotspot : NAN;
+    g_smi.metrics_t = now;
     return GT_OK;
 }
 
@@ -119,6 +213,7 @@ int sensor_open() {
 void sensor_close() {
     std::lock_guard<std::mutex> lk(g_mu);
     if (g_smi.open) {
+        if (g_smi.hwmon_fd >= 0) close(g_smi.hwmon_fd);
         amdsmi_shut_down();
         g_smi = Smi();
     }
@@ -143,6 +238,7 @@ int sensor_read(gt_sensor_sample *out) {
         g_fake.last_p = p;
         out->power_w = p;
         out->energy_j = g_fake.e_j;
+        out->energy_t_s = out->t_s;
         out->sclk_mhz = f;
         out->mclk_mhz = NAN;
         out->volt_v = NAN;
@@ -151,28 +247,15 @@ int sensor_read(gt_sensor_sample *out) {
     }
     int rc = smi_open_locked();
     if (rc) return rc;
-    amdsmi_gpu_metrics_t m;
-    amdsmi_status_t s = amdsmi_get_gpu_metrics_info(g_smi.h, &m);
-    if (s != AMDSMI_STATUS_SUCCESS) return set_error(GT_E_SENSOR, "gpu metrics: %s", smi_str(s));
-    const uint16_t NA16 = 0xFFFF;
-    out->power_w = m.current_socket_power != NA16 ? (double)m.current_socket_power
-                                                  : (m.average_socket_power != NA16 ? (double)m.average_socket_power : NAN);
-    // energy accumulator: unwrap if it ever goes backwards
-    if (m.energy_accumulator < g_smi.last_energy_raw)
-        g_smi.energy_wrap_j += (double)g_smi.last_energy_raw * g_smi.energy_res_j;
-    g_smi.last_energy_raw = m.energy_accumulator;
-    out->energy_j = g_smi.energy_wrap_j + (double)m.energy_accumulator * g_smi.energy_res_j;
-    double sum = 0;
-    int cnt = 0;
-    for (int i = 0; i < AMDSMI_MAX_NUM_GFX_CLKS; ++i)
-        if (m.current_gfxclks[i] != NA16 && m.current_gfxclks[i] != 0) {
-            sum += m.current_gfxclks[i];
-            ++cnt;
-        }
-    out->sclk_mhz = cnt ? sum / cnt : (m.current_gfxclk != NA16 ? (double)m.current_gfxclk : NAN);
-    out->mclk_mhz = m.current_uclk != NA16 ? (double)m.current_uclk : NAN;
-    out->volt_v = (m.voltage_gfx != NA16 && m.voltage_gfx != 0) ? m.voltage_gfx * 1e-3 : NAN;
-    out->temp_c = m.temperature_hotspot != NA16 ? (double)m.temperature_hotspot : NAN;
+    rc = refresh_metrics_locked(out->t_s);
+    if (rc) return rc;
+    const double t = out->t_s;
+    *out = g_smi.cached;
+    out->t_s = t;
+    if (g_smi.hwmon_fd >= 0) {
+        const double p = read_hwmon_w(g_smi.hwmon_fd);
+        if (std::isfinite(p)) out->power_w = p;
+    }
     return GT_OK;
 }
 

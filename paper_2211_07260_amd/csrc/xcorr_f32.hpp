@@ -77,6 +77,34 @@ __device__ __forceinline__ void fma_row(float (&acc)[TY][TX], int r, const float
         for (int c = 0; c < TX; ++c) acc[r][c] = __builtin_fmaf(row[c + j], wr[j], acc[r][c]);
 }
 
+// Store a thread's TY x TX tile at (y, x).  Full tiles of aligned rows use
+// 16-byte stores; otherwise each element is bounds-checked.
+template <int TX, int TY>
+__device__ __forceinline__ void store_tile(const float (&acc)[TY][TX], float *out, int out_h, int out_w,
+                                           int y, int x, bool full) {
+    if constexpr (TX % 4 == 0) {
+        if (full) {
+#pragma unroll
+            for (int r = 0; r < TY; ++r) {
+                float4 *dst = reinterpret_cast<float4 *>(out + (size_t)(y + r) * out_w + x);
+#pragma unroll
+                for (int k = 0; k < TX / 4; ++k)
+                    dst[k] = make_float4(acc[r][4 * k], acc[r][4 * k + 1], acc[r][4 * k + 2], acc[r][4 * k + 3]);
+            }
+            return;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < TY; ++r) {
+        if (y + r < out_h) {
+            float *dst = out + (size_t)(y + r) * out_w;
+#pragma unroll
+            for (int c = 0; c < TX; ++c)
+                if (x + c < out_w) dst[x + c] = acc[r][c];
+        }
+    }
+}
+
 struct XcorrArgs {
     const float *in;
     const float *w;
@@ -84,6 +112,7 @@ struct XcorrArgs {
     int32_t out_h, out_w, in_h, in_w, fh;
     int32_t lds_pitch;  // floats (read path 0)
     int32_t vec_ok;     // input base pointer is 16-byte aligned
+    int32_t out_vec_ok; // output base pointer 16-byte aligned and out_w % 4 == 0
 };
 
 template <int TX, int TY, int FW, int RP>
@@ -93,7 +122,9 @@ __global__ __launch_bounds__(1024) void xcorr_f32_kernel(XcorrArgs a) {
     const int lx = threadIdx.x * TX, ly = threadIdx.y * TY;
     const int x0 = blockIdx.x * bx * TX, y0 = blockIdx.y * by * TY;
     const int fh = a.fh;
-    const float *__restrict__ w = a.w;
+    // The filter is read through the constant address space: its wave-uniform
+    // loads become scalar loads into SGPRs regardless of other memory traffic.
+    const __attribute__((address_space(4))) float *w = (const __attribute__((address_space(4))) float *)a.w;
 
     float acc[TY][TX];
 #pragma unroll
@@ -107,29 +138,45 @@ __global__ __launch_bounds__(1024) void xcorr_f32_kernel(XcorrArgs a) {
         const int tile_w = bx * TX + FW - 1;
         const int tile_h = by * TY + fh - 1;
         const float *__restrict__ in = a.in;
-        // Stage the halo; rows and columns past the input are clamped (their
-        // outputs are never stored).  16-byte loads when rows are aligned.
-        const bool vec = a.vec_ok && ((a.in_w & 3) == 0) && ((x0 & 3) == 0);
+        // Stage the halo as 16-byte chunks.  Interior blocks (the common case)
+        // read whole chunks with no clamping, four chunks in flight per
+        // thread; blocks at the right or bottom edge clamp every element
+        // (values past the input only feed outputs that are never stored).
         const int tid_x = threadIdx.x, tid_y = threadIdx.y;
-        if (vec) {
-            const int tw4 = (tile_w + 3) >> 2;
-            for (int r = tid_y; r < tile_h; r += by) {
-                const int gy = min(y0 + r, a.in_h - 1);
-                const float *src = in + (size_t)gy * a.in_w;
-                float *dst = lds + r * pitch;
-                for (int c4 = tid_x; c4 < tw4; c4 += bx) {
-                    const int gx = x0 + 4 * c4;
-                    float4 v;
-                    if (gx + 3 < a.in_w) {
-                        v = *reinterpret_cast<const float4 *>(src + gx);
-                    } else {
-                        v.x = src[min(gx + 0, a.in_w - 1)];
-                        v.y = src[min(gx + 1, a.in_w - 1)];
-                        v.z = src[min(gx + 2, a.in_w - 1)];
-                        v.w = src[min(gx + 3, a.in_w - 1)];
+        const int nthr = bx * by, tid = tid_y * bx + tid_x;
+        const int tw4 = (tile_w + 3) >> 2;
+        const int nchunks = tile_h * tw4;
+        const bool interior = a.vec_ok && ((a.in_w & 3) == 0) && ((x0 & 3) == 0) &&
+                              x0 + 4 * tw4 <= a.in_w && y0 + tile_h <= a.in_h;
+        if (interior) {
+            // Chunk k of the tile is row k / tw4, column k % tw4; a thread
+            // walks k = tid, tid + nthr, ... keeping (row, column) updated
+            // incrementally.  Loads past the tile re-read chunk 0 (in bounds)
+            // so the four loads issue back to back; their stores are skipped.
+            const float4 *src4 = reinterpret_cast<const float4 *>(in + (size_t)y0 * a.in_w + x0);
+            float4 *lds4 = reinterpret_cast<float4 *>(lds);
+            const int in_w4 = a.in_w >> 2, pitch4 = pitch >> 2;
+            const int dr = nthr / tw4, dc = nthr - dr * tw4;
+            int r = tid / tw4, c = tid - r * tw4;
+            for (int idx = tid; idx < nchunks; idx += 4 * nthr) {
+                float4 v[4];
+                int off[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool ok = idx + u * nthr < nchunks;
+                    v[u] = src4[ok ? r * in_w4 + c : 0];
+                    off[u] = ok ? r * pitch4 + c : -1;
+                    c += dc;
+                    r += dr;
+                    if (c >= tw4) {
+                        c -= tw4;
+                        ++r;
                     }
-                    *reinterpret_cast<float4 *>(dst + 4 * c4) = v;
                 }
+                __builtin_amdgcn_sched_barrier(0);  // keep the four loads ahead of the stores
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (off[u] >= 0) lds4[off[u]] = v[u];
             }
         } else {
             for (int r = tid_y; r < tile_h; r += by) {
@@ -154,18 +201,8 @@ __global__ __launch_bounds__(1024) void xcorr_f32_kernel(XcorrArgs a) {
                 fma_row<TX, TY, FW>(acc, r, row, wr);
             }
         }
-#pragma unroll
-        for (int r = 0; r < TY; ++r) {
-            const int y = y0 + ly + r;
-            if (y < a.out_h) {
-                float *dst = a.out + (size_t)y * a.out_w;
-#pragma unroll
-                for (int c = 0; c < TX; ++c) {
-                    const int x = x0 + lx + c;
-                    if (x < a.out_w) dst[x] = acc[r][c];
-                }
-            }
-        }
+        store_tile<TX, TY>(acc, a.out, a.out_h, a.out_w, y0 + ly, x0 + lx,
+                           a.out_vec_ok && x0 + bx * TX <= a.out_w && y0 + by * TY <= a.out_h);
     } else {
         // Direct read path.  A thread whose tile hangs over the right or
         // bottom edge computes the tile shifted back inside the output (same

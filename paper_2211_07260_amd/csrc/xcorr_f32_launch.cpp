@@ -98,6 +98,7 @@ int launch_xcorr_f32(const gt_problem &p, const gt_conv_config &c, const void *i
     const int64_t tw = (int64_t)c.block_size_x * c.tile_size_x + p.filt_w - 1;
     a.lds_pitch = (int32_t)((tw + 3) / 4 * 4 + 4 * (c.use_lds_padding ? 1 : 0));
     a.vec_ok = (((uintptr_t)in & 15) == 0) ? 1 : 0;
+    a.out_vec_ok = ((((uintptr_t)out & 15) == 0) && (p.out_w % 4 == 0)) ? 1 : 0;
     const int64_t ox = (int64_t)c.block_size_x * c.tile_size_x;
     const int64_t oy = (int64_t)c.block_size_y * c.tile_size_y;
     dim3 grid((unsigned)((p.out_w + ox - 1) / ox), (unsigned)((p.out_h + oy - 1) / oy));

@@ -1,0 +1,232 @@
+"""Tuner drivers over the C ABI: sensor characterisation, exhaustive sweep of
+the restricted tune space, objective selection, and the model-steered clock
+search (sections III-V of the paper).
+
+All measurement, fitting and selection arithmetic runs in the native library
+(measure_time_energy, fit_power_model, gt_power_model_band, gt_select); this
+module only loops, records and reports.
+"""
+import json
+import math
+import os
+import time
+
+import paper_2211_07260_amd as gt
+
+CONV_SPACE = dict(block_size_x=[16, 32, 64, 128], block_size_y=[1, 2, 4, 8, 16],
+                  tile_size_x=list(range(1, 9)), tile_size_y=list(range(1, 9)),
+                  use_lds_padding=[0, 1], read_path=[0, 1])
+
+
+def cfg_key(cfg):
+    return ",".join(str(v) for v in gt.as_config(cfg).as_tuple())
+
+
+# ---- sensor characterisation (the analog of the paper's Fig. 2 power trace) ----
+
+def characterise_sensor(problem, cfg, d_in, d_w, d_out, idle_s=1.0, busy_s=2.5, batch=20):
+    """Record sensor readings while idle, then while the kernel runs
+    back-to-back.  Returns the trace and derived figures: refresh interval of
+    the power reading, idle and loaded medians, and the stabilisation time
+    (first time after the load starts from which the 50 ms rolling median stays
+    within 3 % of the final loaded median)."""
+    import torch
+    trace = []
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < idle_s:
+        s = gt.sensor_read()
+        trace.append(("idle", time.perf_counter() - t0, s))
+        time.sleep(0.0005)
+    t_load = time.perf_counter() - t0
+    k = 0
+    while time.perf_counter() - t0 < idle_s + busy_s:
+        for _ in range(batch):
+            gt.conv2d_run(problem, cfg, d_in, d_w, d_out)
+        k += 1
+        if k % 8 == 0:
+            torch.cuda.synchronize()
+        s = gt.sensor_read()
+        trace.append(("busy", time.perf_counter() - t0, s))
+    torch.cuda.synchronize()
+    pw = [(t, s["power_w"]) for ph, t, s in trace]
+    changes = [pw[i][0] for i in range(1, len(pw)) if pw[i][1] != pw[i - 1][1]]
+    dts = sorted(changes[i] - changes[i - 1] for i in range(1, len(changes)))
+    busy = [(t, p) for (ph, t, s), (_, p) in zip(trace, pw) if ph == "busy"]
+    idle = [p for (ph, t, s), (_, p) in zip(trace, pw) if ph == "idle"]
+    final = sorted(p for t, p in busy if t > idle_s + busy_s - 0.5)
+    p_final = final[len(final) // 2] if final else float("nan")
+    # 50 ms rolling median of the loaded readings; stabilisation = first time
+    # after which every rolling median stays within 3 % of the final median
+    roll = []
+    for i, (t, p) in enumerate(busy):
+        w = sorted(q for u, q in busy[i:] if u - t < 0.05)
+        roll.append((t, w[len(w) // 2]))
+    stab = None
+    for t, med in reversed(roll):
+        if abs(med - p_final) > 0.03 * p_final:
+            break
+        stab = t - t_load
+    return {
+        "refresh_interval_s": dts[len(dts) // 2] if dts else None,
+        "n_readings": len(trace), "n_changes": len(changes),
+        "p_idle_median_w": sorted(idle)[len(idle) // 2] if idle else None,
+        "p_load_median_w": p_final, "stabilisation_s": stab,
+        "trace": [(ph, round(t, 5), s["power_w"], s["sclk_mhz"], s["temp_c"]) for ph, t, s in trace],
+    }
+
+
+# ---- exhaustive sweep ----
+
+def sweep(problem, configs, d_in, d_w, d_out, clk=None, window_s=0.3, discard_s=0.1, log_path=None,
+          resume=True, progress_every=50, time_only=False, repeats=20):
+    """Measure every config (at one clock knob).  Rows are appended to a JSONL
+    log when log_path is given; with resume, configs already in the log are
+    skipped.  time_only: time with HIP events only (no sensor), for the
+    performance landscape."""
+    import torch
+    done = {}
+    if log_path and resume and os.path.exists(log_path):
+        with open(log_path) as fh:
+            for ln in fh:
+                r = json.loads(ln)
+                done[(r["config_key"], r.get("clock", "default"))] = r
+    clk_name = "default" if clk is None or clk.kind == gt.CLOCK_DEFAULT else "%d:%d" % (clk.kind, clk.value)
+    rows = []
+    fh = open(log_path, "a") if log_path else None
+    t0 = time.perf_counter()
+    try:
+        for i, cfg in enumerate(configs):
+            key = cfg_key(cfg)
+            if (key, clk_name) in done:
+                rows.append(done[(key, clk_name)])
+                continue
+            row = {"config": list(gt.as_config(cfg).as_tuple()), "config_key": key, "clock": clk_name}
+            try:
+                if time_only:
+                    for _ in range(2):
+                        gt.conv2d_run(problem, cfg, d_in, d_w, d_out, clk)
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for _ in range(repeats):
+                        gt.conv2d_run(problem, cfg, d_in, d_w, d_out, clk)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    t = e0.elapsed_time(e1) * 1e-3 / repeats
+                    row.update(t_run_s=t, gflops=gt.problem_flops(problem) / t * 1e-9)
+                else:
+                    m = gt.measure_time_energy(problem, cfg, d_in, d_w, d_out, clk, window_s=window_s,
+                                               discard_s=discard_s)
+                    row.update(m)
+            except gt.GreentuneError as e:
+                row["error"] = str(e)
+                row["error_code"] = e.code
+            rows.append(row)
+            if fh:
+                fh.write(json.dumps(row) + "\n")
+                fh.flush()
+            if progress_every and (i + 1) % progress_every == 0:
+                ok = [r for r in rows if "error" not in r]
+                best = min(ok, key=lambda r: r["t_run_s"]) if ok else None
+                print("sweep %d/%d  %.0f s  best %s %.1f GFLOP/s" % (
+                    i + 1, len(configs), time.perf_counter() - t0, best["config"] if best else None,
+                    best["gflops"] if best else 0), flush=True)
+    finally:
+        if fh:
+            fh.close()
+    return rows
+
+
+def optima(rows):
+    """Time-optimal (race-to-idle) and energy-optimal rows, chosen by the
+    library's gt_select (ties: the other objective, then index)."""
+    ok = [r for r in rows if "error" not in r and "e_run_j" in r]
+    if not ok:
+        return None, None
+    recs = [{"t_run_s": r["t_run_s"], "e_run_j": r["e_run_j"]} for r in ok]
+    return ok[gt.select(recs, "time")], ok[gt.select(recs, "energy")]
+
+
+def pareto(rows):
+    """Non-dominated rows in (GFLOP/s, GFLOP/s/W)."""
+    ok = [r for r in rows if "error" not in r and "e_run_j" in r]
+    out = []
+    for a in ok:
+        if not any(b["t_run_s"] <= a["t_run_s"] and b["e_run_j"] <= a["e_run_j"]
+                   and (b["t_run_s"] < a["t_run_s"] or b["e_run_j"] < a["e_run_j"]) for b in ok):
+            out.append(a)
+    return sorted(out, key=lambda r: r["t_run_s"])
+
+
+# ---- model-steered clock search (section V.D) ----
+
+def fit_clocks(settable, n=5):
+    """n clocks spaced uniformly over the settable range, snapped to settable
+    values (the paper samples the supported clocks uniformly)."""
+    s = sorted(settable)
+    lo, hi = s[0], s[-1]
+    out = []
+    for k in range(n):
+        target = lo + (hi - lo) * k / max(n - 1, 1)
+        snap = min(s, key=lambda f: (abs(f - target), f))
+        if snap not in out:
+            out.append(snap)
+    return out
+
+
+def steered_search(measure, configs, settable, p_max, n_fit=5, rel_half=0.1, fit_config=None):
+    """The paper's procedure: fit Eq. 2/3 to <= n_fit power readings of one
+    fully-loading config at uniformly spaced clocks, take the clock minimising
+    P*(f)/f, and measure the candidate configs only at the settable clocks
+    within +-rel_half of it.
+
+    measure(config, clock_mhz) -> dict with t_run_s, e_run_j, p_median_w,
+    sclk_act_mhz, throttled.  Returns a report dict."""
+    fit_config = fit_config or configs[0]
+    fit_pts = []
+    for f in fit_clocks(settable, n_fit):
+        m = measure(fit_config, f)
+        fit_pts.append({"clock_mhz": f, **m})
+    use = [p for p in fit_pts if not p.get("throttled")]
+    model = gt.fit_power_model([p["clock_mhz"] for p in use], [p["p_median_w"] for p in use], p_max)
+    f_opt, band = gt.power_model_band(model, settable, rel_half)
+    rows = []
+    for cfg in configs:
+        for f in band:
+            m = measure(cfg, f)
+            rows.append({"config": list(gt.as_config(cfg).as_tuple()), "clock_mhz": f, **m})
+    best = min(rows, key=lambda r: (r["e_run_j"], r["t_run_s"]))
+    return {"fit_points": fit_pts, "model": model.as_dict(), "f_opt_mhz": f_opt, "band_mhz": band,
+            "rows": rows, "best": best, "points_measured_band": len(rows),
+            "points_measured_total": len(rows) + len(fit_pts)}
+
+
+def exhaustive_clock_search(measure, configs, settable):
+    rows = []
+    for cfg in configs:
+        for f in settable:
+            m = measure(cfg, f)
+            rows.append({"config": list(gt.as_config(cfg).as_tuple()), "clock_mhz": f, **m})
+    best = min(rows, key=lambda r: (r["e_run_j"], r["t_run_s"]))
+    return {"rows": rows, "best": best, "points_measured": len(rows)}
+
+
+def hardware_measure(problem, d_in, d_w, d_out, window_s=1.0, discard_s=0.3):
+    """measure(config, clock) over the real DVFS knob (needs privileges)."""
+    def measure(cfg, f_mhz):
+        return gt.measure_time_energy(problem, cfg, d_in, d_w, d_out, gt.clock(gt.CLOCK_SCLK_MHZ, f_mhz),
+                                      window_s=window_s, discard_s=discard_s)
+    return measure
+
+
+def gain_pct(before, after):
+    return (after / before - 1.0) * 100.0
+
+
+def nan_to_none(obj):
+    if isinstance(obj, float) and (math.isnan(obj) or math.isinf(obj)):
+        return None
+    if isinstance(obj, dict):
+        return {k: nan_to_none(v) for k, v in obj.items()}
+    if isinstance(obj, (list, tuple)):
+        return [nan_to_none(v) for v in obj]
+    return obj
