@@ -242,6 +242,42 @@ int gt_dvfs_state(gt_clock *current);
  * when no kernel is running in the window. */
 int gt_fake_sensor_model(const gt_power_model *model, double noise_w, uint64_t seed);
 
+/* ---- batching: many convolutions in one persistent launch ---- */
+
+/* One single-channel FP32 cross-correlation of a batch (layouts as for
+ * GT_XCORR_F32; all device pointers). */
+typedef struct {
+    const void *d_in, *d_filt;
+    void *d_out;
+    int32_t out_h, out_w, filt_h, filt_w;
+} gt_batch_item;
+
+/* Pack n_items convolutions into a device-ready descriptor blob (48 bytes per
+ * item) written to host_blob[0..capacity); the caller copies it to device
+ * memory (8-byte aligned) and passes that copy to conv2d_run_batched.  All
+ * items must share one square filter size (3, 5, 9 or 17); cfg must use the
+ * LDS read path with tile sizes in {1, 2, 4, 8}.  *blob_bytes and
+ * *total_tiles (workgroup tiles over all items) are always written;
+ * GT_E_CAPACITY if capacity < *blob_bytes. */
+int gt_batch_pack(const gt_batch_item *items, int32_t n_items, const gt_conv_config *cfg, void *host_blob,
+                  size_t capacity, size_t *blob_bytes, int64_t *total_tiles);
+
+/* One persistent launch over every tile of a packed batch: grid_blocks
+ * workgroups (0 = resident capacity of the device) stride over the tile
+ * list.  Each output equals, bit for bit, what conv2d_run with the same
+ * config writes.  Launch only (no allocation, no memset), so it may be
+ * captured in a graph.  Errors: GT_E_INVAL, GT_E_UNSUPPORTED, GT_E_HIP. */
+int conv2d_run_batched(const void *d_blob, int32_t n_items, int64_t total_tiles, int32_t filt,
+                       const gt_conv_config *cfg, int32_t grid_blocks, void *hip_stream);
+
+/* Graph capture of the launches issued on hip_stream between begin and end
+ * (hipStreamBeginCapture / EndCapture / Instantiate).  *graph_exec is an
+ * opaque executable graph owned by the caller until gt_graph_destroy. */
+int gt_graph_begin(void *hip_stream);
+int gt_graph_end(void *hip_stream, void **graph_exec);
+int gt_graph_launch(void *graph_exec, void *hip_stream);
+int gt_graph_destroy(void *graph_exec);
+
 /* ---- roofline probes ---- */
 
 /* Measure the achievable FP32 vector FMA rate (FMA with one SGPR operand, the

@@ -83,6 +83,12 @@ class PowerModel(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("d_in", ctypes.c_void_p), ("d_filt", ctypes.c_void_p), ("d_out", ctypes.c_void_p),
+                ("out_h", ctypes.c_int32), ("out_w", ctypes.c_int32), ("filt_h", ctypes.c_int32),
+                ("filt_w", ctypes.c_int32)]
+
+
 class SensorSample(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in ("t_s", "power_w", "energy_j", "energy_t_s", "sclk_mhz",
                                                "mclk_mhz", "volt_v", "temp_c")]
@@ -135,6 +141,14 @@ def _load():
         "gt_dvfs_state": ([P(Clock)], c_int),
         "gt_fake_sensor_model": ([P(PowerModel), c_double, ctypes.c_uint64], c_int),
         "gt_roofline_probe": ([vp, c_size, vp, P(c_double), P(c_double)], c_int),
+        "gt_batch_pack": ([P(BatchItem), ctypes.c_int32, P(ConvConfig), vp, c_size, P(c_size),
+                           P(ctypes.c_int64)], c_int),
+        "conv2d_run_batched": ([vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P(ConvConfig),
+                                ctypes.c_int32, vp], c_int),
+        "gt_graph_begin": ([vp], c_int),
+        "gt_graph_end": ([vp, P(vp)], c_int),
+        "gt_graph_launch": ([vp, vp], c_int),
+        "gt_graph_destroy": ([vp], c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -148,7 +162,8 @@ EXPORTED = ("gt_init", "gt_shutdown", "gt_last_error", "gt_version", "conv2d_run
             "tune_space_enumerate", "measure_time_energy", "fit_power_model", "gt_power_model_eval",
             "gt_power_model_band", "gt_energy_from_samples", "gt_select", "gt_problem_flops",
             "gt_conv_lds_bytes", "gt_sensor_read", "gt_settable_clocks", "gt_dvfs_state",
-            "gt_fake_sensor_model", "gt_roofline_probe")
+            "gt_fake_sensor_model", "gt_roofline_probe", "gt_batch_pack", "conv2d_run_batched",
+            "gt_graph_begin", "gt_graph_end", "gt_graph_launch", "gt_graph_destroy")
 
 
 def lib():
@@ -350,3 +365,64 @@ def roofline_probe(buf, stream=None):
     _check(_lib.gt_roofline_probe(_ptr(buf), buf.numel() * buf.element_size(), _stream(stream),
                                   ctypes.byref(t), ctypes.byref(g)))
     return t.value, g.value
+
+
+# ---- batching ----
+
+class Batch:
+    """A packed batch of single-channel convolutions sharing one filter size
+    and config.  convs: list of (d_in, d_filt, d_out, out_h, out_w, f) with
+    torch device tensors.  The descriptor blob lives in a device tensor owned
+    by this object."""
+
+    def __init__(self, convs, cfg):
+        import torch
+        self.cfg = as_config(cfg)
+        items = (BatchItem * len(convs))()
+        for k, (di, dw, do, oh, ow, f) in enumerate(convs):
+            items[k] = BatchItem(di.data_ptr(), dw.data_ptr(), do.data_ptr(), oh, ow, f, f)
+        self.n = len(convs)
+        self.filt = convs[0][5]
+        nb, tt = ctypes.c_size_t(0), ctypes.c_int64(0)
+        rc = _lib.gt_batch_pack(items, self.n, ctypes.byref(self.cfg), None, 0, ctypes.byref(nb), ctypes.byref(tt))
+        if rc not in (GT_OK, GT_E_CAPACITY):
+            _check(rc)
+        host = torch.empty(nb.value, dtype=torch.uint8)
+        _check(_lib.gt_batch_pack(items, self.n, ctypes.byref(self.cfg), ctypes.c_void_p(host.data_ptr()),
+                                  nb.value, ctypes.byref(nb), ctypes.byref(tt)))
+        self.total_tiles = tt.value
+        self.blob = host.to(convs[0][0].device)
+        self._keep = convs  # the device buffers must outlive the batch
+
+    def run(self, grid_blocks=0, stream=None):
+        _check(_lib.conv2d_run_batched(_ptr(self.blob), self.n, self.total_tiles, self.filt, ctypes.byref(self.cfg),
+                                       grid_blocks, _stream(stream)))
+
+
+class Graph:
+    """Executable graph of the launches issued by fn() on a side stream."""
+
+    def __init__(self, fn, stream):
+        self.stream = stream
+        h = ctypes.c_void_p(0)
+        _check(_lib.gt_graph_begin(_stream(stream)))
+        try:
+            fn()
+        finally:
+            rc = _lib.gt_graph_end(_stream(stream), ctypes.byref(h))
+        _check(rc)
+        self.handle = h
+
+    def launch(self):
+        _check(_lib.gt_graph_launch(self.handle, _stream(self.stream)))
+
+    def close(self):
+        if self.handle:
+            _check(_lib.gt_graph_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass

@@ -1,0 +1,299 @@
+// Multi-channel convolution as an implicit GEMM (no im2col buffer).
+//
+//   out[b][y][x][k] = sum_{r,s,c} in[b][y+r-ph][x+s-pw][c] * wt[k][r][s][c]
+//
+// with NHWC activations, KRSC weights and an NHWC FP32 output.  Seen as a
+// GEMM, M = batch*out_h*out_w output pixels, N = c_out, and the reduction runs
+// over (r, s, c).  Two kernels:
+//
+// * BF16 on MFMA (v_mfma_f32_16x16x32_bf16, FP32 accumulate).  A fragment
+//   lane l holds A[m = l%16][k = 8*(l/16) .. +8]: with NHWC input that is 16
+//   contiguous bytes of one pixel's channels, and the KRSC weight fragment
+//   B[k = 8*(l/16) .. +8][n = l%16] is likewise 16 contiguous bytes, so both
+//   operands are loaded straight from memory with one 16-byte load per lane
+//   and no transposition.  A wave owns 4 M-tiles (64 pixels) x NT N-tiles
+//   (16*NT output channels); the fragments of the next (r, s, c-block) step
+//   are loaded while the current step's MFMAs issue.  Zero padding is a
+//   masked load (the address is clamped in bounds, the value replaced by 0).
+//
+// * FP32 on the vector ALUs, the comparison path.  Lanes are output channels
+//   (64 per wave) and a wave owns P pixels, so an input value is the same for
+//   the whole wave: it is read with scalar loads into SGPRs and each FMA is
+//   v_fmac acc, s_x, v_w with the weights in VGPRs (read through L1/L2).
+#include <hip/hip_runtime.h>
+
+#include "gt_internal.hpp"
+
+namespace gt {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+struct IgemmArgs {
+    const void *in;
+    const void *w;
+    float *out;
+    int32_t n, h, wd, c_in, c_out, out_h, out_w, ph, pw;
+    int32_t m_total;  // n * out_h * out_w
+};
+
+constexpr int kMfmaWaves = 4, kMT = 4;  // waves per workgroup, 16-pixel M-tiles per wave
+
+template <int R, int S, int C, int NT>
+__global__ __launch_bounds__(256) void igemm_bf16_mfma_kernel(IgemmArgs a) {
+    constexpr int KC = C / 32;         // 32-channel reduction blocks per (r, s)
+    constexpr int STEPS = R * S * KC;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int m_wave = (blockIdx.x * kMfmaWaves + wave) * (16 * kMT);
+    const int n_blk = blockIdx.y * (16 * NT);
+    const unsigned short *in = static_cast<const unsigned short *>(a.in);
+    const unsigned short *wt = static_cast<const unsigned short *>(a.w);
+
+    // this lane's A pixels (row li of each M-tile)
+    int pb[kMT], py[kMT], px[kMT];
+    bool pv[kMT];
+#pragma unroll
+    for (int t = 0; t < kMT; ++t) {
+        int m = m_wave + t * 16 + li;
+        pv[t] = m < a.m_total;
+        m = pv[t] ? m : 0;
+        px[t] = m % a.out_w;
+        const int q = m / a.out_w;
+        py[t] = q % a.out_h;
+        pb[t] = q / a.out_h;
+    }
+
+    auto load_step = [&](int step, u32x4 (&A)[kMT], u32x4 (&B)[NT]) {
+        const int kc = step % KC, rs = step / KC;
+        const int s = rs % S, r = rs / S;
+        const int c0 = kc * 32 + lg * 8;
+#pragma unroll
+        for (int t = 0; t < kMT; ++t) {
+            const int yy = py[t] + r - a.ph, xx = px[t] + s - a.pw;
+            const bool ok = pv[t] && yy >= 0 && yy < a.h && xx >= 0 && xx < a.wd;
+            const size_t off = ok ? (((size_t)pb[t] * a.h + yy) * a.wd + xx) * C + c0 : 0;
+            const u32x4 v = *reinterpret_cast<const u32x4 *>(in + off);
+            A[t] = ok ? v : u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int co = n_blk + j * 16 + li;
+            B[j] = *reinterpret_cast<const u32x4 *>(wt + (((size_t)co * R + r) * S + s) * C + c0);
+        }
+    };
+
+    f32x4 acc[kMT][NT];
+#pragma unroll
+    for (int t = 0; t < kMT; ++t)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    u32x4 A0[kMT], B0[NT], A1[kMT], B1[NT];
+    load_step(0, A0, B0);
+#pragma unroll
+    for (int step = 0; step < STEPS; step += 2) {
+        if (step + 1 < STEPS) load_step(step + 1, A1, B1);
+#pragma unroll
+        for (int t = 0; t < kMT; ++t)
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf16x8, A0[t]), __builtin_bit_cast(bf16x8, B0[j]), acc[t][j], 0, 0, 0);
+        if (step + 1 < STEPS) {
+            if (step + 2 < STEPS) load_step(step + 2, A0, B0);
+#pragma unroll
+            for (int t = 0; t < kMT; ++t)
+#pragma unroll
+                for (int j = 0; j < NT; ++j)
+                    acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, A1[t]), __builtin_bit_cast(bf16x8, B1[j]), acc[t][j], 0, 0,
+                        0);
+        }
+    }
+
+    // D[m = 4*lg + e][n = li]: for fixed e, 16 lanes store 16 consecutive channels
+#pragma unroll
+    for (int t = 0; t < kMT; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int m = m_wave + t * 16 + lg * 4 + e;
+            if (m < a.m_total) {
+                float *dst = a.out + (size_t)m * a.c_out + n_blk + li;
+#pragma unroll
+                for (int j = 0; j < NT; ++j) dst[j * 16] = acc[t][j][e];
+            }
+        }
+}
+
+constexpr int kValuP = 8, kValuWaves = 4;  // pixels per wave, waves per workgroup
+
+// A wave computes kValuP consecutive output pixels of one output row (all
+// 64 output channels of its channel block, one per lane).  The input row
+// pointer and the row check are wave-uniform; in interior tiles every pixel
+// of a filter tap is valid and its 8-channel input chunk is one scalar load
+// at a compile-time offset from the row pointer.
+template <int R, int S, int C>
+__global__ __launch_bounds__(256) void igemm_f32_valu_kernel(IgemmArgs a) {
+    typedef const __attribute__((address_space(4))) float cfloat;
+    const float *__restrict__ wt = static_cast<const float *>(a.w);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tiles_x = (a.out_w + kValuP - 1) / kValuP;
+    const int tile = blockIdx.x * kValuWaves + wave;
+    const int row = tile / tiles_x;                      // b * out_h + y
+    const int x0 = (tile - row * tiles_x) * kValuP;
+    const int co = blockIdx.y * 64 + lane;
+    if (row >= a.n * a.out_h) return;  // wave-uniform: past the last row
+    const int b = row / a.out_h, y = row - b * a.out_h;
+
+    float acc[kValuP];
+#pragma unroll
+    for (int p = 0; p < kValuP; ++p) acc[p] = 0.f;
+
+    for (int r = 0; r < R; ++r) {
+        const int yy = y + r - a.ph;
+        if (yy < 0 || yy >= a.h) continue;  // zero padding rows
+        cfloat *rowp = (cfloat *)a.in + ((size_t)b * a.h + yy) * a.wd * C;
+#pragma unroll 1
+        for (int s = 0; s < S; ++s) {
+            const int xs = x0 + s - a.pw;  // input column of pixel 0
+            const float *wrs = wt + (((size_t)co * R + r) * S + s) * C;
+            const bool all = xs >= 0 && xs + kValuP <= a.wd;
+#pragma unroll 1
+            for (int c = 0; c < C; c += 8) {  // one 8-channel chunk: 8 pixels x 8 inputs in SGPRs
+                float wv[8];
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const float4 v = *reinterpret_cast<const float4 *>(wrs + c + 4 * k);
+                    wv[4 * k] = v.x;
+                    wv[4 * k + 1] = v.y;
+                    wv[4 * k + 2] = v.z;
+                    wv[4 * k + 3] = v.w;
+                }
+                if (all) {
+                    cfloat *px = rowp + (size_t)xs * C + c;
+#pragma unroll
+                    for (int p = 0; p < kValuP; ++p)
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) acc[p] = __builtin_fmaf(px[p * C + k], wv[k], acc[p]);
+                } else {
+#pragma unroll
+                    for (int p = 0; p < kValuP; ++p) {
+                        const int xx = xs + p;
+                        if (xx >= 0 && xx < a.wd) {
+                            cfloat *px = rowp + (size_t)xx * C + c;
+#pragma unroll
+                            for (int k = 0; k < 8; ++k) acc[p] = __builtin_fmaf(px[k], wv[k], acc[p]);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    float *dst = a.out + (size_t)row * a.out_w * a.c_out + co;
+#pragma unroll
+    for (int p = 0; p < kValuP; ++p)
+        if (x0 + p < a.out_w) dst[(size_t)(x0 + p) * a.c_out] = acc[p];
+}
+
+namespace {
+
+template <int R, int S>
+const void *pick_mfma(int c, int nt) {
+    if (c == 64 && nt == 4) return (const void *)&igemm_bf16_mfma_kernel<R, S, 64, 4>;
+    if (c == 64 && nt == 2) return (const void *)&igemm_bf16_mfma_kernel<R, S, 64, 2>;
+    if (c == 32 && nt == 4) return (const void *)&igemm_bf16_mfma_kernel<R, S, 32, 4>;
+    if (c == 32 && nt == 2) return (const void *)&igemm_bf16_mfma_kernel<R, S, 32, 2>;
+    return nullptr;
+}
+
+const void *mfma_kernel_for(int f, int c, int c_out) {
+    const int nt = (c_out % 64 == 0) ? 4 : 2;
+    switch (f) {
+        case 1: return pick_mfma<1, 1>(c, nt);
+        case 3: return pick_mfma<3, 3>(c, nt);
+        case 5: return pick_mfma<5, 5>(c, nt);
+        case 7: return pick_mfma<7, 7>(c, nt);
+        default: return nullptr;
+    }
+}
+
+template <int R, int S>
+const void *pick_valu(int c) {
+    if (c == 64) return (const void *)&igemm_f32_valu_kernel<R, S, 64>;
+    if (c == 32) return (const void *)&igemm_f32_valu_kernel<R, S, 32>;
+    return nullptr;
+}
+
+const void *valu_kernel_for(int f, int c) {
+    switch (f) {
+        case 1: return pick_valu<1, 1>(c);
+        case 3: return pick_valu<3, 3>(c);
+        case 5: return pick_valu<5, 5>(c);
+        case 7: return pick_valu<7, 7>(c);
+        default: return nullptr;
+    }
+}
+
+}  // namespace
+
+int validate_igemm(const gt_problem &p, const gt_conv_config &) {
+    if (p.n < 1 || p.c_in < 1 || p.c_out < 1 || p.out_h < 1 || p.out_w < 1 || p.filt_h < 1 || p.filt_w < 1 ||
+        p.pad_h < 0 || p.pad_w < 0)
+        return set_error(GT_E_INVAL, "igemm: sizes must be positive and padding non-negative");
+    const int64_t h = (int64_t)p.out_h + p.filt_h - 1 - 2 * p.pad_h;
+    const int64_t w = (int64_t)p.out_w + p.filt_w - 1 - 2 * p.pad_w;
+    if (h < 1 || w < 1) return set_error(GT_E_INVAL, "igemm: padding larger than the input allows");
+    if ((int64_t)p.n * h * w * p.c_in >= (int64_t)1 << 31 || (int64_t)p.n * p.out_h * p.out_w >= (int64_t)1 << 31)
+        return set_error(GT_E_INVAL, "igemm: problem too large for 32-bit pixel indexing");
+    if (p.filt_h != p.filt_w) return set_error(GT_E_UNSUPPORTED, "igemm: square filters only");
+    if (p.kind == GT_IGEMM_BF16_MFMA) {
+        if (p.c_out % 32 != 0) return set_error(GT_E_UNSUPPORTED, "igemm bf16: c_out must be a multiple of 32");
+        if (!mfma_kernel_for(p.filt_h, p.c_in, p.c_out))
+            return set_error(GT_E_UNSUPPORTED, "igemm bf16: c_in %d / filter %d not instantiated (c_in 32 or 64; "
+                             "filter 1, 3, 5, 7)", p.c_in, p.filt_h);
+    } else {
+        if (p.c_out % 64 != 0) return set_error(GT_E_UNSUPPORTED, "igemm f32: c_out must be a multiple of 64");
+        if (!valu_kernel_for(p.filt_h, p.c_in))
+            return set_error(GT_E_UNSUPPORTED, "igemm f32: c_in %d / filter %d not instantiated (c_in 32 or 64; "
+                             "filter 1, 3, 5, 7)", p.c_in, p.filt_h);
+    }
+    return GT_OK;
+}
+
+int launch_igemm(const gt_problem &p, const gt_conv_config &, const void *in, const void *w, void *out,
+                 hipStream_t s) {
+    if ((((uintptr_t)in) | ((uintptr_t)w)) & 15)
+        return set_error(GT_E_INVAL, "igemm: input and weights must be 16-byte aligned");
+    IgemmArgs a;
+    a.in = in;
+    a.w = w;
+    a.out = static_cast<float *>(out);
+    a.n = p.n;
+    a.h = p.out_h + p.filt_h - 1 - 2 * p.pad_h;
+    a.wd = p.out_w + p.filt_w - 1 - 2 * p.pad_w;
+    a.c_in = p.c_in;
+    a.c_out = p.c_out;
+    a.out_h = p.out_h;
+    a.out_w = p.out_w;
+    a.ph = p.pad_h;
+    a.pw = p.pad_w;
+    a.m_total = p.n * p.out_h * p.out_w;
+    void *args[] = {&a};
+    if (p.kind == GT_IGEMM_BF16_MFMA) {
+        const int nt = (p.c_out % 64 == 0) ? 4 : 2;
+        const int per_wg = kMfmaWaves * kMT * 16;
+        dim3 grid((unsigned)((a.m_total + per_wg - 1) / per_wg), (unsigned)(p.c_out / (16 * nt)));
+        GT_HIP_CHECK(hipLaunchKernel(mfma_kernel_for(p.filt_h, p.c_in, p.c_out), grid, dim3(256), args, 0, s));
+    } else {
+        const int64_t tiles = (int64_t)p.n * p.out_h * ((p.out_w + kValuP - 1) / kValuP);
+        dim3 grid((unsigned)((tiles + kValuWaves - 1) / kValuWaves), (unsigned)(p.c_out / 64));
+        GT_HIP_CHECK(hipLaunchKernel(valu_kernel_for(p.filt_h, p.c_in), grid, dim3(256), args, 0, s));
+    }
+    return GT_OK;
+}
+
+}  // namespace gt

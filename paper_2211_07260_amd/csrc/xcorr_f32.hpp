@@ -115,12 +115,14 @@ struct XcorrArgs {
     int32_t out_vec_ok; // output base pointer 16-byte aligned and out_w % 4 == 0
 };
 
-template <int TX, int TY, int FW, int RP>
-__global__ __launch_bounds__(1024) void xcorr_f32_kernel(XcorrArgs a) {
+// One workgroup tile whose top-left output is (x0, y0), LDS read path.  Used
+// by the one-launch-per-convolution kernel and by the persistent batched
+// kernel, so both produce bit-identical outputs.
+template <int TX, int TY, int FW>
+__device__ __forceinline__ void xcorr_tile_lds(const XcorrArgs &a, int x0, int y0, float *lds) {
     constexpr int RW = TX + FW - 1;  // input row segment per thread
     const int bx = blockDim.x, by = blockDim.y;
     const int lx = threadIdx.x * TX, ly = threadIdx.y * TY;
-    const int x0 = blockIdx.x * bx * TX, y0 = blockIdx.y * by * TY;
     const int fh = a.fh;
     // The filter is read through the constant address space: its wave-uniform
     // loads become scalar loads into SGPRs regardless of other memory traffic.
@@ -131,108 +133,129 @@ __global__ __launch_bounds__(1024) void xcorr_f32_kernel(XcorrArgs a) {
     for (int r = 0; r < TY; ++r)
 #pragma unroll
         for (int c = 0; c < TX; ++c) acc[r][c] = 0.0f;
-
-    if constexpr (RP == 0) {
-        extern __shared__ __align__(16) float lds[];
-        const int pitch = a.lds_pitch;
-        const int tile_w = bx * TX + FW - 1;
-        const int tile_h = by * TY + fh - 1;
-        const float *__restrict__ in = a.in;
-        // Stage the halo as 16-byte chunks.  Interior blocks (the common case)
-        // read whole chunks with no clamping, four chunks in flight per
-        // thread; blocks at the right or bottom edge clamp every element
-        // (values past the input only feed outputs that are never stored).
-        const int tid_x = threadIdx.x, tid_y = threadIdx.y;
-        const int nthr = bx * by, tid = tid_y * bx + tid_x;
-        const int tw4 = (tile_w + 3) >> 2;
-        const int nchunks = tile_h * tw4;
-        const bool interior = a.vec_ok && ((a.in_w & 3) == 0) && ((x0 & 3) == 0) &&
-                              x0 + 4 * tw4 <= a.in_w && y0 + tile_h <= a.in_h;
-        if (interior) {
-            // Chunk k of the tile is row k / tw4, column k % tw4; a thread
-            // walks k = tid, tid + nthr, ... keeping (row, column) updated
-            // incrementally.  Loads past the tile re-read chunk 0 (in bounds)
-            // so the four loads issue back to back; their stores are skipped.
-            const float4 *src4 = reinterpret_cast<const float4 *>(in + (size_t)y0 * a.in_w + x0);
-            float4 *lds4 = reinterpret_cast<float4 *>(lds);
-            const int in_w4 = a.in_w >> 2, pitch4 = pitch >> 2;
-            const int dr = nthr / tw4, dc = nthr - dr * tw4;
-            int r = tid / tw4, c = tid - r * tw4;
-            for (int idx = tid; idx < nchunks; idx += 4 * nthr) {
-                float4 v[4];
-                int off[4];
+    const int pitch = a.lds_pitch;
+    const int tile_w = bx * TX + FW - 1;
+    const int tile_h = by * TY + fh - 1;
+    const float *__restrict__ in = a.in;
+    // Stage the halo as 16-byte chunks.  Interior blocks (the common case)
+    // read whole chunks with no clamping, four chunks in flight per
+    // thread; blocks at the right or bottom edge clamp every element
+    // (values past the input only feed outputs that are never stored).
+    const int tid_x = threadIdx.x, tid_y = threadIdx.y;
+    const int nthr = bx * by, tid = tid_y * bx + tid_x;
+    const int tw4 = (tile_w + 3) >> 2;
+    const int nchunks = tile_h * tw4;
+    const bool interior = a.vec_ok && ((a.in_w & 3) == 0) && ((x0 & 3) == 0) &&
+                          x0 + 4 * tw4 <= a.in_w && y0 + tile_h <= a.in_h;
+    if (interior) {
+        // Chunk k of the tile is row k / tw4, column k % tw4; a thread
+        // walks k = tid, tid + nthr, ... keeping (row, column) updated
+        // incrementally.  Loads past the tile re-read chunk 0 (in bounds)
+        // so the four loads issue back to back; their stores are skipped.
+        const float4 *src4 = reinterpret_cast<const float4 *>(in + (size_t)y0 * a.in_w + x0);
+        float4 *lds4 = reinterpret_cast<float4 *>(lds);
+        const int in_w4 = a.in_w >> 2, pitch4 = pitch >> 2;
+        const int dr = nthr / tw4, dc = nthr - dr * tw4;
+        int r = tid / tw4, c = tid - r * tw4;
+        for (int idx = tid; idx < nchunks; idx += 4 * nthr) {
+            float4 v[4];
+            int off[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const bool ok = idx + u * nthr < nchunks;
-                    v[u] = src4[ok ? r * in_w4 + c : 0];
-                    off[u] = ok ? r * pitch4 + c : -1;
-                    c += dc;
-                    r += dr;
-                    if (c >= tw4) {
-                        c -= tw4;
-                        ++r;
-                    }
+            for (int u = 0; u < 4; ++u) {
+                const bool ok = idx + u * nthr < nchunks;
+                v[u] = src4[ok ? r * in_w4 + c : 0];
+                off[u] = ok ? r * pitch4 + c : -1;
+                c += dc;
+                r += dr;
+                if (c >= tw4) {
+                    c -= tw4;
+                    ++r;
                 }
-                __builtin_amdgcn_sched_barrier(0);  // keep the four loads ahead of the stores
+            }
+            __builtin_amdgcn_sched_barrier(0);  // keep the four loads ahead of the stores
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (off[u] >= 0) lds4[off[u]] = v[u];
-            }
-        } else {
-            for (int r = tid_y; r < tile_h; r += by) {
-                const int gy = min(y0 + r, a.in_h - 1);
-                const float *src = in + (size_t)gy * a.in_w;
-                float *dst = lds + r * pitch;
-                for (int c = tid_x; c < tile_w; c += bx) dst[c] = src[min(x0 + c, a.in_w - 1)];
-            }
+            for (int u = 0; u < 4; ++u)
+                if (off[u] >= 0) lds4[off[u]] = v[u];
         }
-        __syncthreads();
-
-        constexpr int V = RowVec<TX>::value;
-        const float *base = lds + ly * pitch + lx;
-        for (int i = 0; i < fh; ++i) {
-            float wr[FW];
-#pragma unroll
-            for (int j = 0; j < FW; ++j) wr[j] = w[i * FW + j];
-#pragma unroll
-            for (int r = 0; r < TY; ++r) {
-                float row[RW];
-                load_row_lds<RW, V>(row, base + (r + i) * pitch);
-                fma_row<TX, TY, FW>(acc, r, row, wr);
-            }
-        }
-        store_tile<TX, TY>(acc, a.out, a.out_h, a.out_w, y0 + ly, x0 + lx,
-                           a.out_vec_ok && x0 + bx * TX <= a.out_w && y0 + by * TY <= a.out_h);
     } else {
-        // Direct read path.  A thread whose tile hangs over the right or
-        // bottom edge computes the tile shifted back inside the output (same
-        // sums, in-bounds reads) and stores only its own outputs.
-        const int xt = x0 + lx, yt = y0 + ly;
-        const int xs = min(xt, a.out_w - TX), ys = min(yt, a.out_h - TY);
-        const float *base = a.in + (size_t)ys * a.in_w + xs;
-        for (int i = 0; i < fh; ++i) {
-            float wr[FW];
-#pragma unroll
-            for (int j = 0; j < FW; ++j) wr[j] = w[i * FW + j];
-#pragma unroll
-            for (int r = 0; r < TY; ++r) {
-                float row[RW];
-                load_row_global<RW>(row, base + (size_t)(r + i) * a.in_w);
-                fma_row<TX, TY, FW>(acc, r, row, wr);
-            }
+        for (int r = tid_y; r < tile_h; r += by) {
+            const int gy = min(y0 + r, a.in_h - 1);
+            const float *src = in + (size_t)gy * a.in_w;
+            float *dst = lds + r * pitch;
+            for (int c = tid_x; c < tile_w; c += bx) dst[c] = src[min(x0 + c, a.in_w - 1)];
         }
+    }
+    __syncthreads();
+
+    constexpr int V = RowVec<TX>::value;
+    const float *base = lds + ly * pitch + lx;
+    for (int i = 0; i < fh; ++i) {
+        float wr[FW];
+#pragma unroll
+        for (int j = 0; j < FW; ++j) wr[j] = w[i * FW + j];
 #pragma unroll
         for (int r = 0; r < TY; ++r) {
-            const int y = ys + r;
-            if (y >= yt) {
-                float *dst = a.out + (size_t)y * a.out_w;
+            float row[RW];
+            load_row_lds<RW, V>(row, base + (r + i) * pitch);
+            fma_row<TX, TY, FW>(acc, r, row, wr);
+        }
+    }
+    store_tile<TX, TY>(acc, a.out, a.out_h, a.out_w, y0 + ly, x0 + lx,
+                       a.out_vec_ok && x0 + bx * TX <= a.out_w && y0 + by * TY <= a.out_h);
+}
+
+// One workgroup tile, direct read path (no LDS).
+template <int TX, int TY, int FW>
+__device__ __forceinline__ void xcorr_tile_direct(const XcorrArgs &a, int x0, int y0) {
+    constexpr int RW = TX + FW - 1;
+    const int lx = threadIdx.x * TX, ly = threadIdx.y * TY;
+    const int fh = a.fh;
+    const __attribute__((address_space(4))) float *w = (const __attribute__((address_space(4))) float *)a.w;
+
+    float acc[TY][TX];
 #pragma unroll
-                for (int c = 0; c < TX; ++c) {
-                    const int x = xs + c;
-                    if (x >= xt) dst[x] = acc[r][c];
-                }
+    for (int r = 0; r < TY; ++r)
+#pragma unroll
+        for (int c = 0; c < TX; ++c) acc[r][c] = 0.0f;
+    // Direct read path.  A thread whose tile hangs over the right or
+    // bottom edge computes the tile shifted back inside the output (same
+    // sums, in-bounds reads) and stores only its own outputs.
+    const int xt = x0 + lx, yt = y0 + ly;
+    const int xs = min(xt, a.out_w - TX), ys = min(yt, a.out_h - TY);
+    const float *base = a.in + (size_t)ys * a.in_w + xs;
+    for (int i = 0; i < fh; ++i) {
+        float wr[FW];
+#pragma unroll
+        for (int j = 0; j < FW; ++j) wr[j] = w[i * FW + j];
+#pragma unroll
+        for (int r = 0; r < TY; ++r) {
+            float row[RW];
+            load_row_global<RW>(row, base + (size_t)(r + i) * a.in_w);
+            fma_row<TX, TY, FW>(acc, r, row, wr);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < TY; ++r) {
+        const int y = ys + r;
+        if (y >= yt) {
+            float *dst = a.out + (size_t)y * a.out_w;
+#pragma unroll
+            for (int c = 0; c < TX; ++c) {
+                const int x = xs + c;
+                if (x >= xt) dst[x] = acc[r][c];
             }
         }
+    }
+}
+
+template <int TX, int TY, int FW, int RP>
+__global__ __launch_bounds__(1024) void xcorr_f32_kernel(XcorrArgs a) {
+    const int x0 = blockIdx.x * blockDim.x * TX, y0 = blockIdx.y * blockDim.y * TY;
+    if constexpr (RP == 0) {
+        extern __shared__ __align__(16) float lds[];
+        xcorr_tile_lds<TX, TY, FW>(a, x0, y0, lds);
+    } else {
+        xcorr_tile_direct<TX, TY, FW>(a, x0, y0);
     }
 }
 

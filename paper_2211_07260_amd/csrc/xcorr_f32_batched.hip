@@ -1,0 +1,216 @@
+// Persistent batched FP32 cross-correlation: many convolutions in one launch.
+//
+// The host packs a descriptor per convolution (pointers, sizes, and the
+// index of its first tile in the concatenated tile list).  A grid sized to
+// the device's resident capacity walks the tile list with a static stride
+// (item = blockIdx.x, blockIdx.x + gridDim.x, ...): no counters, so the
+// launch can be captured in a graph and replayed as is.  Each item runs the
+// same LDS tile body as the one-launch-per-convolution kernel, so a
+// convolution's output is bit-identical whether it runs alone or batched.
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "gt_internal.hpp"
+#include "xcorr_f32.hpp"
+
+namespace gt {
+
+struct BatchDesc {
+    const float *in;
+    const float *w;
+    float *out;
+    int32_t out_h, out_w;
+    int32_t tiles_x;
+    int32_t flags;       // bit 0: input 16-byte aligned; bit 1: output aligned and out_w % 4 == 0
+    int64_t tile_begin;  // first tile of this convolution in the batch
+};
+static_assert(sizeof(BatchDesc) == 48, "descriptor layout");
+
+template <int TX, int TY, int FW>
+__global__ __launch_bounds__(1024) void xcorr_f32_batched_kernel(const BatchDesc *__restrict__ desc, int n_desc,
+                                                                 int64_t total_tiles, int lds_pitch) {
+    extern __shared__ __align__(16) float lds[];
+    typedef const __attribute__((address_space(4))) BatchDesc cdesc;
+    cdesc *d = (cdesc *)desc;
+    for (int64_t item = blockIdx.x; item < total_tiles; item += gridDim.x) {
+        // the convolution holding this tile: last descriptor with tile_begin <= item
+        int lo = 0, hi = n_desc - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (d[mid].tile_begin <= item)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int64_t local = item - d[lo].tile_begin;
+        const int ty = (int)(local / d[lo].tiles_x), tx = (int)(local - (int64_t)ty * d[lo].tiles_x);
+        XcorrArgs a;
+        a.in = d[lo].in;
+        a.w = d[lo].w;
+        a.out = d[lo].out;
+        a.out_h = d[lo].out_h;
+        a.out_w = d[lo].out_w;
+        a.in_h = a.out_h + FW - 1;
+        a.in_w = a.out_w + FW - 1;
+        a.fh = FW;
+        a.lds_pitch = lds_pitch;
+        a.vec_ok = d[lo].flags & 1;
+        a.out_vec_ok = (d[lo].flags >> 1) & 1;
+        __syncthreads();  // the previous item's LDS tile is no longer read
+        xcorr_tile_lds<TX, TY, FW>(a, tx * blockDim.x * TX, ty * blockDim.y * TY, lds);
+    }
+}
+
+namespace {
+
+struct BatchEntry {
+    int tx, ty, fw;
+    const void *fn;
+};
+
+#define GT_B(TX, TY, FW) {TX, TY, FW, (const void *)&xcorr_f32_batched_kernel<TX, TY, FW>}
+#define GT_B_FW(TX, TY) GT_B(TX, TY, 3), GT_B(TX, TY, 5), GT_B(TX, TY, 9), GT_B(TX, TY, 17)
+#define GT_B_TY(TX) GT_B_FW(TX, 1), GT_B_FW(TX, 2), GT_B_FW(TX, 4), GT_B_FW(TX, 8)
+const BatchEntry kBatchTable[] = {GT_B_TY(1), GT_B_TY(2), GT_B_TY(4), GT_B_TY(8)};
+#undef GT_B_TY
+#undef GT_B_FW
+#undef GT_B
+
+const void *batched_fn(int tx, int ty, int fw) {
+    for (const BatchEntry &e : kBatchTable)
+        if (e.tx == tx && e.ty == ty && e.fw == fw) return e.fn;
+    return nullptr;
+}
+
+int validate_batch_config(const gt_conv_config &c, int fw) {
+    if (c.read_path != 0) return set_error(GT_E_UNSUPPORTED, "batched: LDS read path only");
+    if (c.block_size_x < 1 || c.block_size_y < 1) return set_error(GT_E_INVAL, "batched: bad block size");
+    if ((int64_t)c.block_size_x * c.block_size_y > state().dev.max_threads)
+        return set_error(GT_E_UNSUPPORTED, "batched: too many threads per block");
+    if (!batched_fn(c.tile_size_x, c.tile_size_y, fw))
+        return set_error(GT_E_UNSUPPORTED, "batched: tile %dx%d / filter %d not instantiated (tiles 1, 2, 4, 8; "
+                         "filters 3, 5, 9, 17)", c.tile_size_x, c.tile_size_y, fw);
+    return GT_OK;
+}
+
+int64_t batch_lds_bytes(const gt_conv_config &c, int fw) {
+    gt_problem p{GT_XCORR_F32, 1, 1, 1, 1, 1, fw, fw, 0, 0};
+    return xcorr_lds_bytes(p, c);
+}
+
+}  // namespace
+}  // namespace gt
+
+using namespace gt;
+
+extern "C" {
+
+int gt_batch_pack(const gt_batch_item *items, int32_t n_items, const gt_conv_config *cfg, void *host_blob,
+                  size_t capacity, size_t *blob_bytes, int64_t *total_tiles) {
+    clear_error();
+    if (!items || n_items < 1 || !cfg || !blob_bytes || !total_tiles || (capacity && !host_blob))
+        return set_error(GT_E_INVAL, "gt_batch_pack: bad argument");
+    const int fw = items[0].filt_w;
+    int rc = validate_batch_config(*cfg, fw);
+    if (rc) return rc;
+    const size_t need = sizeof(BatchDesc) * (size_t)n_items;
+    *blob_bytes = need;
+    std::vector<BatchDesc> d((size_t)n_items);
+    int64_t tiles = 0;
+    const int64_t ox = (int64_t)cfg->block_size_x * cfg->tile_size_x, oy = (int64_t)cfg->block_size_y * cfg->tile_size_y;
+    for (int32_t k = 0; k < n_items; ++k) {
+        const gt_batch_item &it = items[k];
+        if (!it.d_in || !it.d_filt || !it.d_out || it.out_h < 1 || it.out_w < 1)
+            return set_error(GT_E_INVAL, "gt_batch_pack: item %d is not valid", k);
+        if (it.filt_h != fw || it.filt_w != fw)
+            return set_error(GT_E_INVAL, "gt_batch_pack: item %d: all items need the same square filter (%d)", k, fw);
+        if ((int64_t)(it.out_h + fw - 1) * (it.out_w + fw - 1) >= (int64_t)1 << 31)
+            return set_error(GT_E_INVAL, "gt_batch_pack: item %d too large", k);
+        const int64_t tx = (it.out_w + ox - 1) / ox, ty = (it.out_h + oy - 1) / oy;
+        d[k].in = static_cast<const float *>(it.d_in);
+        d[k].w = static_cast<const float *>(it.d_filt);
+        d[k].out = static_cast<float *>(it.d_out);
+        d[k].out_h = it.out_h;
+        d[k].out_w = it.out_w;
+        d[k].tiles_x = (int32_t)tx;
+        d[k].flags = ((((uintptr_t)it.d_in & 15) == 0) ? 1 : 0) |
+                     (((((uintptr_t)it.d_out & 15) == 0) && it.out_w % 4 == 0) ? 2 : 0);
+        d[k].tile_begin = tiles;
+        tiles += tx * ty;
+    }
+    *total_tiles = tiles;
+    if (capacity < need) return set_error(GT_E_CAPACITY, "gt_batch_pack: %zu bytes needed", need);
+    memcpy(host_blob, d.data(), need);
+    return GT_OK;
+}
+
+int conv2d_run_batched(const void *d_blob, int32_t n_items, int64_t total_tiles, int32_t filt,
+                       const gt_conv_config *cfg, int32_t grid_blocks, void *hip_stream) {
+    clear_error();
+    if (!d_blob || n_items < 1 || total_tiles < 1 || !cfg)
+        return set_error(GT_E_INVAL, "conv2d_run_batched: bad argument");
+    if (!state().inited || (state().flags & GT_INIT_HOST_ONLY))
+        return set_error(GT_E_STATE, "conv2d_run_batched: needs gt_init on a device");
+    if ((uintptr_t)d_blob & 7) return set_error(GT_E_INVAL, "conv2d_run_batched: descriptor blob must be 8-byte aligned");
+    int rc = validate_batch_config(*cfg, filt);
+    if (rc) return rc;
+    const int64_t lds = batch_lds_bytes(*cfg, filt);
+    if (lds > state().dev.lds_per_block) return set_error(GT_E_UNSUPPORTED, "conv2d_run_batched: LDS tile too large");
+    const void *fn = batched_fn(cfg->tile_size_x, cfg->tile_size_y, filt);
+    if (lds > 65536) GT_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int threads = cfg->block_size_x * cfg->block_size_y;
+    if (grid_blocks <= 0) {
+        int per_cu = 0;
+        GT_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, (size_t)lds));
+        grid_blocks = std::max(1, per_cu) * std::max(1, state().dev.cu_count);
+    }
+    const int64_t grid = std::min<int64_t>(grid_blocks, total_tiles);
+    const int pitch = (int)((cfg->block_size_x * cfg->tile_size_x + filt - 1 + 3) / 4 * 4 +
+                            4 * (cfg->use_lds_padding ? 1 : 0));
+    const BatchDesc *desc = static_cast<const BatchDesc *>(d_blob);
+    int n = n_items;
+    int64_t tt = total_tiles;
+    void *args[] = {&desc, &n, &tt, (void *)&pitch};
+    GT_HIP_CHECK(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(cfg->block_size_x, cfg->block_size_y), args,
+                                 (size_t)lds, (hipStream_t)hip_stream));
+    return GT_OK;
+}
+
+// ---- graph capture of a launch sequence ----
+
+int gt_graph_begin(void *hip_stream) {
+    clear_error();
+    if (!hip_stream) return set_error(GT_E_INVAL, "gt_graph_begin: capture needs a non-null stream");
+    GT_HIP_CHECK(hipStreamBeginCapture((hipStream_t)hip_stream, hipStreamCaptureModeThreadLocal));
+    return GT_OK;
+}
+
+int gt_graph_end(void *hip_stream, void **graph_exec) {
+    clear_error();
+    if (!hip_stream || !graph_exec) return set_error(GT_E_INVAL, "gt_graph_end: bad argument");
+    hipGraph_t g = nullptr;
+    GT_HIP_CHECK(hipStreamEndCapture((hipStream_t)hip_stream, &g));
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return set_error(GT_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    *graph_exec = ex;
+    return GT_OK;
+}
+
+int gt_graph_launch(void *graph_exec, void *hip_stream) {
+    clear_error();
+    if (!graph_exec) return set_error(GT_E_INVAL, "gt_graph_launch: null graph");
+    GT_HIP_CHECK(hipGraphLaunch((hipGraphExec_t)graph_exec, (hipStream_t)hip_stream));
+    return GT_OK;
+}
+
+int gt_graph_destroy(void *graph_exec) {
+    clear_error();
+    if (graph_exec) GT_HIP_CHECK(hipGraphExecDestroy((hipGraphExec_t)graph_exec));
+    return GT_OK;
+}
+
+}  // extern "C"

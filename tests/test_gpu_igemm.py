@@ -1,0 +1,100 @@
+"""GPU parity of the multi-channel implicit-GEMM convolutions against the FP64
+oracle, through the C ABI.  Inputs are BF16 values (N(0,1) rounded); the
+FP32 VALU path consumes the same values widened to FP32.  Bars: normwise max
+relative error <= 2e-2 for the BF16 MFMA path and <= 1e-5 for the FP32 path
+(both accumulate in FP32 over exactly representable products, so both land
+near 1e-7 in practice)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synthetic import conv_inputs
+
+pytestmark = pytest.mark.gpu
+TOL = {1: 2e-2, 2: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def gt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2211_07260_amd as g
+    g.init(0, 0)
+    yield g
+    g.shutdown()
+
+
+def run(gt, kind, x, wt, pad):
+    n, h, w, ci = x.shape
+    co, fh, fw, _ = wt.shape
+    dev = torch.device("cuda:0")
+    if kind == gt.IGEMM_BF16_MFMA:
+        dx, dw = x.to(dev).contiguous(), wt.to(dev).contiguous()
+    else:
+        dx, dw = x.float().to(dev).contiguous(), wt.float().to(dev).contiguous()
+    oh, ow = h + 2 * pad - fh + 1, w + 2 * pad - fw + 1
+    out = torch.full((n, oh, ow, co), float("nan"), dtype=torch.float32, device=dev)
+    p = gt.Problem(kind, n, ci, co, oh, ow, fh, fw, pad, pad)
+    gt.conv2d_run(p, (64, 1, 1, 1, 0, 0), dx, dw, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+CASES = [  # n, h, w, c_in, c_out, f
+    (2, 9, 13, 64, 64, 3), (1, 16, 16, 64, 64, 5), (3, 7, 11, 32, 32, 3), (2, 12, 10, 32, 64, 5),
+    (1, 5, 37, 64, 32, 1), (1, 8, 9, 64, 128, 7), (1, 3, 3, 32, 32, 5), (2, 20, 17, 64, 64, 3),
+]
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("case", CASES)
+def test_igemm_parity_ragged(gt, kind, case):
+    n, h, w, ci, co, f = case
+    if kind == 2 and co % 64:
+        pytest.skip("FP32 VALU path needs c_out % 64 == 0")
+    x, wt = conv_inputs(n, h, w, ci, co, f, f, seed=sum(case))
+    pad = (f - 1) // 2
+    ref = oracle.conv_nhwc(x.float().numpy(), wt.float().numpy(), pad, pad)
+    print("case:", kind, case, flush=True)
+    got = run(gt, kind, x, wt, pad)
+    err = oracle.max_rel_err(got, ref)
+    print("max rel err %.3e" % err, flush=True)
+    assert err <= TOL[kind]
+
+
+def test_igemm_valid_padding_zero(gt):
+    # pad 0: output shrinks by f-1 (both kinds)
+    x, wt = conv_inputs(1, 12, 14, 64, 64, 3, 3, seed=5)
+    ref = oracle.conv_nhwc(x.float().numpy(), wt.float().numpy(), 0, 0)
+    for kind in (1, 2):
+        got = run(gt, kind, x, wt, 0)
+        assert got.shape == ref.shape
+        assert oracle.max_rel_err(got, ref) <= TOL[kind]
+
+
+@pytest.mark.parametrize("f", [3, 5])
+def test_igemm_full_size_sampled(gt, f):
+    # benchmark shape: N=16, C=64, K=64, 128x128, same padding; compare images 0 and 15 fully
+    x, wt = conv_inputs(16, 128, 128, 64, 64, f, f, seed=0)
+    pad = (f - 1) // 2
+    refs = {b: oracle.conv_nhwc(x[b:b + 1].float().numpy(), wt.float().numpy(), pad, pad) for b in (0, 15)}
+    for kind in (1, 2):
+        print("case: full f=%d kind=%d" % (f, kind), flush=True)
+        got = run(gt, kind, x, wt, pad)
+        for b, ref in refs.items():
+            err = oracle.max_rel_err(got[b:b + 1], ref)
+            print("image %d max rel err %.3e" % (b, err), flush=True)
+            assert err <= TOL[kind]
+        assert np.isfinite(got).all()
+
+
+def test_igemm_unsupported(gt):
+    x, wt = conv_inputs(1, 8, 8, 48, 64, 3, 3)
+    with pytest.raises(gt.GreentuneError) as e:
+        run(gt, 1, x, wt, 1)
+    assert e.value.code == gt.GT_E_UNSUPPORTED
+    x, wt = conv_inputs(1, 8, 8, 64, 32, 3, 3)
+    with pytest.raises(gt.GreentuneError) as e:
+        run(gt, 2, x, wt, 1)
+    assert e.value.code == gt.GT_E_UNSUPPORTED
