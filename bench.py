@@ -3,6 +3,8 @@
 Workload: single-channel FP32 cross-correlation, output 4096 x 4096, filter
 17 x 17, input 4112 x 4112, uniform[0,1) from seed 0 (synthetic).  One step =
 one launch of the kernel with the tuned configuration, inputs resident in HBM.
+The warm-up (about half a second of launches) brings the graphics clock to its
+loaded level before the timed region.
 The energy efficiency (GFLOP/s/W) of the same configuration is measured after
 the timed region with the library's measure_time_energy (median socket power
 times time per run).  Prints one JSON line.
@@ -50,14 +52,41 @@ def cpu_baseline(img, w, min_seconds=8.0):
             "sample": "full 4096x4096x17x17 FP64 cross-correlation x%d (%.1f s wall)" % (reps, el)}
 
 
+def igemm_extras(gt, torch, dev, steps=20):
+    """Multi-channel conv (N=16, C_in=C_out=64, 128x128, same padding), BF16
+    MFMA and FP32 VALU paths on the same BF16-valued data: ms and TFLOP/s."""
+    from synthetic import conv_inputs
+    res = {}
+    for f in (3, 5):
+        x, wt = conv_inputs(16, 128, 128, 64, 64, f, f, seed=0)
+        out = torch.empty(16, 128, 128, 64, dtype=torch.float32, device=dev)
+        for kind, name, xx, ww in ((gt.IGEMM_BF16_MFMA, "bf16_mfma", x, wt),
+                                   (gt.IGEMM_F32_VALU, "f32_valu", x.float(), wt.float())):
+            dx, dw = xx.to(dev).contiguous(), ww.to(dev).contiguous()
+            p = gt.conv_problem(kind, 16, 128, 128, 64, 64, f, f)
+            for _ in range(3):
+                gt.conv2d_run(p, (64, 1, 1, 1, 0, 0), dx, dw, out)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                gt.conv2d_run(p, (64, 1, 1, 1, 0, 0), dx, dw, out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            res["%s_f%d" % (name, f)] = {"ms": round(ms, 5), "tflops": round(gt.problem_flops(p) / ms / 1e9, 2)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=3000)
     ap.add_argument("--no-energy", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--config", type=str, default=None, help="bx,by,tx,ty,pad,rp")
+    ap.add_argument("--probe", action="store_true", help="run the roofline probes only")
+    ap.add_argument("--no-extras", action="store_true", help="skip the multi-channel timings")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the tuning method and its kernels run on a single "
@@ -78,9 +107,17 @@ def main():
     else:
         cfg = DEFAULT_CFG
         cfg_src = "default (no committed sweep)"
+    e_cfg = tuple(tuned["energy_optimal"]["config"]) if tuned and not args.config else None
 
     dev = torch.device("cuda:0")
     gt.init(0, 0)
+    if args.probe:
+        buf = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        t, g = gt.roofline_probe(buf)
+        print(json.dumps({"fp32_fma_tflops": t, "copy_gbs": g, "copy_read_bytes_per_launch": 1 << 29,
+                          "copy_write_bytes_per_launch": 1 << 29}), flush=True)
+        gt.shutdown()
+        return
     img, w = xcorr_inputs(4096, 4096, 17, 17, seed=0)
     d_in, d_w = img.to(dev), w.to(dev)
     out = torch.empty(4096, 4096, dtype=torch.float32, device=dev)
@@ -108,15 +145,27 @@ def main():
 
     energy = None
     if not args.no_energy:
-        try:
-            m = gt.measure_time_energy(prob, cfg, d_in, d_w, out, window_s=1.0, discard_s=0.3)
-            energy = {"gflops_per_w": m["gflops_per_w"], "gflops": m["gflops"], "p_median_w": m["p_median_w"],
-                      "e_run_j": m["e_run_j"], "e_run_counter_j": m["e_run_counter_j"],
-                      "sclk_act_mhz": m["sclk_act_mhz"], "temp_c": m["temp_c"], "n_samples": m["n_used"]}
-            print("bench: energy %.2f GFLOP/s/W at %.0f W" % (m["gflops_per_w"], m["p_median_w"]),
-                  file=sys.stderr, flush=True)
-        except gt.GreentuneError as e:
-            energy = {"error": str(e)}
+        energy = {}
+        for name, c in (("time_tuned", cfg), ("energy_tuned", e_cfg)):
+            if c is None:
+                continue
+            try:
+                m = gt.measure_time_energy(prob, c, d_in, d_w, out, window_s=2.0, discard_s=0.4)
+                energy[name] = {"config": list(c), "gflops_per_w": m["gflops_per_w"], "gflops": m["gflops"],
+                                "p_median_w": m["p_median_w"], "e_run_j": m["e_run_j"],
+                                "e_run_counter_j": m["e_run_counter_j"], "sclk_act_mhz": m["sclk_act_mhz"],
+                                "temp_c": m["temp_c"], "n_samples": m["n_used"]}
+                print("bench: %s %.2f GFLOP/s/W at %.0f W" % (name, m["gflops_per_w"], m["p_median_w"]),
+                      file=sys.stderr, flush=True)
+            except gt.GreentuneError as e:
+                energy[name] = {"error": str(e)}
+        if "gflops_per_w" in energy.get("time_tuned", {}) and "gflops_per_w" in energy.get("energy_tuned", {}):
+            energy["efficiency_gain_energy_vs_time"] = (energy["energy_tuned"]["gflops_per_w"]
+                                                        / energy["time_tuned"]["gflops_per_w"])
+
+    extras = None
+    if not args.no_extras:
+        extras = igemm_extras(gt, torch, dev)
 
     traffic = None
     if os.path.exists(TRAFFIC):
@@ -142,8 +191,9 @@ def main():
         "config": {"workload": "xcorr2d FP32 single-channel, out 4096x4096, filter 17x17, uniform[0,1) seed 0",
                    "kernel_config": dict(zip(gt.CONFIG_FIELDS, cfg)), "config_source": cfg_src,
                    "parallelism": "single GPU"},
-        "gflops_per_w": energy.get("gflops_per_w") if energy and "gflops_per_w" in energy else None,
+        "gflops_per_w": (energy or {}).get("time_tuned", {}).get("gflops_per_w"),
         "energy": energy,
+        "multichannel": extras,
         "wall_s_timed": round(t_wall, 4),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),

@@ -230,6 +230,18 @@ int gt_conv_lds_bytes(const gt_problem *problem, const gt_conv_config *config, i
 
 /* One reading of the power sensor (amd-smi GPU metrics, or the fake sensor). */
 int gt_sensor_read(gt_sensor_sample *s);
+/* Background sampler: a native thread reads the sensor every period_ms
+ * from gt_sampler_start until gt_sampler_stop, which joins it and copies up
+ * to capacity samples (oldest first) into out; *n receives the total.
+ * GT_E_CAPACITY if capacity < *n (the first capacity samples are written);
+ * GT_E_SENSOR if no reading succeeded; GT_E_STATE if not started / already
+ * running.  One sampler per process. */
+int gt_sampler_start(double period_ms);
+int gt_sampler_stop(gt_sensor_sample *out, size_t capacity, size_t *n);
+/* Tell the fake sensor whether kernels are running (it reports idle power
+ * otherwise); no effect on the hardware sensor. */
+int gt_sensor_busy(int busy);
+
 /* Settable graphics-clock list in MHz, ascending (DVFS range of the device,
  * at step_mhz spacing; the fake DVFS backend reports 500..2400).
  * GT_E_CAPACITY if cap is too small (*n still written). */

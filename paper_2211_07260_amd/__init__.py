@@ -149,6 +149,9 @@ def _load():
         "gt_graph_end": ([vp, P(vp)], c_int),
         "gt_graph_launch": ([vp, vp], c_int),
         "gt_graph_destroy": ([vp], c_int),
+        "gt_sampler_start": ([c_double], c_int),
+        "gt_sampler_stop": ([P(SensorSample), c_size, P(c_size)], c_int),
+        "gt_sensor_busy": ([c_int], c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -163,7 +166,8 @@ EXPORTED = ("gt_init", "gt_shutdown", "gt_last_error", "gt_version", "conv2d_run
             "gt_power_model_band", "gt_energy_from_samples", "gt_select", "gt_problem_flops",
             "gt_conv_lds_bytes", "gt_sensor_read", "gt_settable_clocks", "gt_dvfs_state",
             "gt_fake_sensor_model", "gt_roofline_probe", "gt_batch_pack", "conv2d_run_batched",
-            "gt_graph_begin", "gt_graph_end", "gt_graph_launch", "gt_graph_destroy")
+            "gt_graph_begin", "gt_graph_end", "gt_graph_launch", "gt_graph_destroy", "gt_sampler_start",
+            "gt_sampler_stop", "gt_sensor_busy")
 
 
 def lib():
@@ -426,3 +430,22 @@ class Graph:
             self.close()
         except Exception:  # noqa: BLE001
             pass
+
+
+# ---- background sampler ----
+
+def sampler_start(period_ms=2.0):
+    _check(_lib.gt_sampler_start(float(period_ms)))
+
+
+def sampler_stop(capacity=1 << 20):
+    arr = (SensorSample * capacity)()
+    n = ctypes.c_size_t(0)
+    rc = _lib.gt_sampler_stop(arr, capacity, ctypes.byref(n))
+    if rc not in (GT_OK, GT_E_CAPACITY):
+        _check(rc)
+    return [arr[k].as_dict() for k in range(min(n.value, capacity))]
+
+
+def sensor_busy(busy):
+    _check(_lib.gt_sensor_busy(1 if busy else 0))

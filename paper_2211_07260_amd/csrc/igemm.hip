@@ -128,6 +128,106 @@ __global__ __launch_bounds__(256) void igemm_bf16_mfma_kernel(IgemmArgs a) {
         }
 }
 
+// Same tile and fragment layout with the filter size a runtime value: the
+// (r, s, c-block) walk is a loop with scalar counters instead of a fully
+// unrolled sequence, for filter sizes without a dedicated instance.
+template <int C, int NT>
+__global__ __launch_bounds__(256) void igemm_bf16_mfma_any_kernel(IgemmArgs a, int R, int S) {
+    constexpr int KC = C / 32;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int m_wave = (blockIdx.x * kMfmaWaves + wave) * (16 * kMT);
+    const int n_blk = blockIdx.y * (16 * NT);
+    const unsigned short *in = static_cast<const unsigned short *>(a.in);
+    const unsigned short *wt = static_cast<const unsigned short *>(a.w);
+
+    int pb[kMT], py[kMT], px[kMT];
+    bool pv[kMT];
+#pragma unroll
+    for (int t = 0; t < kMT; ++t) {
+        int m = m_wave + t * 16 + li;
+        pv[t] = m < a.m_total;
+        m = pv[t] ? m : 0;
+        px[t] = m % a.out_w;
+        const int q = m / a.out_w;
+        py[t] = q % a.out_h;
+        pb[t] = q / a.out_h;
+    }
+    auto load = [&](int r, int s, int kc, u32x4 (&A)[kMT], u32x4 (&B)[NT]) {
+        const int c0 = kc * 32 + lg * 8;
+#pragma unroll
+        for (int t = 0; t < kMT; ++t) {
+            const int yy = py[t] + r - a.ph, xx = px[t] + s - a.pw;
+            const bool ok = pv[t] && yy >= 0 && yy < a.h && xx >= 0 && xx < a.wd;
+            const size_t off = ok ? (((size_t)pb[t] * a.h + yy) * a.wd + xx) * C + c0 : 0;
+            const u32x4 v = *reinterpret_cast<const u32x4 *>(in + off);
+            A[t] = ok ? v : u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int co = n_blk + j * 16 + li;
+            B[j] = *reinterpret_cast<const u32x4 *>(wt + (((size_t)co * R + r) * S + s) * C + c0);
+        }
+    };
+    auto next = [&](int &r, int &s, int &kc) {
+        if (++kc == KC) {
+            kc = 0;
+            if (++s == S) {
+                s = 0;
+                ++r;
+            }
+        }
+    };
+    f32x4 acc[kMT][NT];
+#pragma unroll
+    for (int t = 0; t < kMT; ++t)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int steps = R * S * KC;
+    int r = 0, s = 0, kc = 0;
+    u32x4 A0[kMT], B0[NT], A1[kMT], B1[NT];
+    load(r, s, kc, A0, B0);
+    next(r, s, kc);
+    for (int step = 0; step < steps; step += 2) {
+        const bool more = step + 1 < steps;
+        if (more) {
+            load(r, s, kc, A1, B1);
+            next(r, s, kc);
+        }
+#pragma unroll
+        for (int t = 0; t < kMT; ++t)
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf16x8, A0[t]), __builtin_bit_cast(bf16x8, B0[j]), acc[t][j], 0, 0, 0);
+        if (more) {
+            if (step + 2 < steps) {
+                load(r, s, kc, A0, B0);
+                next(r, s, kc);
+            }
+#pragma unroll
+            for (int t = 0; t < kMT; ++t)
+#pragma unroll
+                for (int j = 0; j < NT; ++j)
+                    acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, A1[t]), __builtin_bit_cast(bf16x8, B1[j]), acc[t][j], 0, 0,
+                        0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kMT; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int m = m_wave + t * 16 + lg * 4 + e;
+            if (m < a.m_total) {
+                float *dst = a.out + (size_t)m * a.c_out + n_blk + li;
+#pragma unroll
+                for (int j = 0; j < NT; ++j) dst[j * 16] = acc[t][j][e];
+            }
+        }
+}
+
 constexpr int kValuP = 8, kValuWaves = 4;  // pixels per wave, waves per workgroup
 
 // A wave computes kValuP consecutive output pixels of one output row (all
@@ -210,15 +310,28 @@ const void *pick_mfma(int c, int nt) {
     return nullptr;
 }
 
-const void *mfma_kernel_for(int f, int c, int c_out) {
+const void *mfma_any_for(int c, int nt) {
+    if (c == 64 && nt == 4) return (const void *)&igemm_bf16_mfma_any_kernel<64, 4>;
+    if (c == 64 && nt == 2) return (const void *)&igemm_bf16_mfma_any_kernel<64, 2>;
+    if (c == 32 && nt == 4) return (const void *)&igemm_bf16_mfma_any_kernel<32, 4>;
+    if (c == 32 && nt == 2) return (const void *)&igemm_bf16_mfma_any_kernel<32, 2>;
+    return nullptr;
+}
+
+// Dedicated fully unrolled instances for filter sizes 1, 3, 5, 7; the
+// runtime-size kernel for the others.  *generic tells which one was chosen.
+const void *mfma_kernel_for(int f, int c, int c_out, bool *generic = nullptr) {
     const int nt = (c_out % 64 == 0) ? 4 : 2;
+    const void *fn = nullptr;
     switch (f) {
-        case 1: return pick_mfma<1, 1>(c, nt);
-        case 3: return pick_mfma<3, 3>(c, nt);
-        case 5: return pick_mfma<5, 5>(c, nt);
-        case 7: return pick_mfma<7, 7>(c, nt);
-        default: return nullptr;
+        case 1: fn = pick_mfma<1, 1>(c, nt); break;
+        case 3: fn = pick_mfma<3, 3>(c, nt); break;
+        case 5: fn = pick_mfma<5, 5>(c, nt); break;
+        case 7: fn = pick_mfma<7, 7>(c, nt); break;
+        default: break;
     }
+    if (generic) *generic = fn == nullptr;
+    return fn ? fn : mfma_any_for(c, nt);
 }
 
 template <int R, int S>
@@ -253,8 +366,7 @@ int validate_igemm(const gt_problem &p, const gt_conv_config &) {
     if (p.kind == GT_IGEMM_BF16_MFMA) {
         if (p.c_out % 32 != 0) return set_error(GT_E_UNSUPPORTED, "igemm bf16: c_out must be a multiple of 32");
         if (!mfma_kernel_for(p.filt_h, p.c_in, p.c_out))
-            return set_error(GT_E_UNSUPPORTED, "igemm bf16: c_in %d / filter %d not instantiated (c_in 32 or 64; "
-                             "filter 1, 3, 5, 7)", p.c_in, p.filt_h);
+            return set_error(GT_E_UNSUPPORTED, "igemm bf16: c_in %d not instantiated (32 or 64)", p.c_in);
     } else {
         if (p.c_out % 64 != 0) return set_error(GT_E_UNSUPPORTED, "igemm f32: c_out must be a multiple of 64");
         if (!valu_kernel_for(p.filt_h, p.c_in))
@@ -287,7 +399,15 @@ int launch_igemm(const gt_problem &p, const gt_conv_config &, const void *in, co
         const int nt = (p.c_out % 64 == 0) ? 4 : 2;
         const int per_wg = kMfmaWaves * kMT * 16;
         dim3 grid((unsigned)((a.m_total + per_wg - 1) / per_wg), (unsigned)(p.c_out / (16 * nt)));
-        GT_HIP_CHECK(hipLaunchKernel(mfma_kernel_for(p.filt_h, p.c_in, p.c_out), grid, dim3(256), args, 0, s));
+        bool generic = false;
+        const void *fn = mfma_kernel_for(p.filt_h, p.c_in, p.c_out, &generic);
+        if (generic) {
+            int R = p.filt_h, S = p.filt_w;
+            void *gargs[] = {&a, &R, &S};
+            GT_HIP_CHECK(hipLaunchKernel(fn, grid, dim3(256), gargs, 0, s));
+        } else {
+            GT_HIP_CHECK(hipLaunchKernel(fn, grid, dim3(256), args, 0, s));
+        }
     } else {
         const int64_t tiles = (int64_t)p.n * p.out_h * ((p.out_w + kValuP - 1) / kValuP);
         dim3 grid((unsigned)((tiles + kValuWaves - 1) / kValuWaves), (unsigned)(p.c_out / 64));

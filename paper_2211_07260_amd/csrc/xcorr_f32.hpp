@@ -157,25 +157,31 @@ __device__ __forceinline__ void xcorr_tile_lds(const XcorrArgs &a, int x0, int y
         const int in_w4 = a.in_w >> 2, pitch4 = pitch >> 2;
         const int dr = nthr / tw4, dc = nthr - dr * tw4;
         int r = tid / tw4, c = tid - r * tw4;
-        for (int idx = tid; idx < nchunks; idx += 4 * nthr) {
-            float4 v[4];
-            int off[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const bool ok = idx + u * nthr < nchunks;
-                v[u] = src4[ok ? r * in_w4 + c : 0];
-                off[u] = ok ? r * pitch4 + c : -1;
-                c += dc;
-                r += dr;
-                if (c >= tw4) {
-                    c -= tw4;
-                    ++r;
-                }
+        // (named registers, not arrays: the scheduling barrier below would
+        // otherwise keep four-element arrays in scratch memory)
+        auto fetch = [&](int idx, float4 &v, int &off) {
+            const bool ok = idx < nchunks;
+            v = src4[ok ? r * in_w4 + c : 0];
+            off = ok ? r * pitch4 + c : -1;
+            c += dc;
+            r += dr;
+            if (c >= tw4) {
+                c -= tw4;
+                ++r;
             }
+        };
+        for (int idx = tid; idx < nchunks; idx += 4 * nthr) {
+            float4 v0, v1, v2, v3;
+            int o0, o1, o2, o3;
+            fetch(idx, v0, o0);
+            fetch(idx + nthr, v1, o1);
+            fetch(idx + 2 * nthr, v2, o2);
+            fetch(idx + 3 * nthr, v3, o3);
             __builtin_amdgcn_sched_barrier(0);  // keep the four loads ahead of the stores
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (off[u] >= 0) lds4[off[u]] = v[u];
+            if (o0 >= 0) lds4[o0] = v0;
+            if (o1 >= 0) lds4[o1] = v1;
+            if (o2 >= 0) lds4[o2] = v2;
+            if (o3 >= 0) lds4[o3] = v3;
         }
     } else {
         for (int r = tid_y; r < tile_h; r += by) {

@@ -230,3 +230,92 @@ def nan_to_none(obj):
     if isinstance(obj, (list, tuple)):
         return [nan_to_none(v) for v in obj]
     return obj
+
+
+# ---- summaries of a sweep (the tuned-config store) ----
+
+SWEEP_CSV_FIELDS = ("block_size_x", "block_size_y", "tile_size_x", "tile_size_y", "use_lds_padding", "read_path",
+                    "t_run_s", "p_median_w", "e_run_j", "e_run_counter_j", "gflops", "gflops_per_w", "sclk_act_mhz",
+                    "temp_c")
+
+
+def write_sweep_csv(rows, path):
+    import csv
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(SWEEP_CSV_FIELDS)
+        for r in rows:
+            if "error" in r:
+                continue
+            w.writerow(list(r["config"]) + ["%.6g" % r[k] if isinstance(r[k], float) else r[k]
+                                            for k in SWEEP_CSV_FIELDS[6:]])
+
+
+def read_sweep_csv(path):
+    import csv
+    rows = []
+    with open(path) as fh:
+        for d in csv.DictReader(fh):
+            cfg = [int(d[k]) for k in SWEEP_CSV_FIELDS[:6]]
+            row = {k: float(d[k]) for k in SWEEP_CSV_FIELDS[6:]}
+            row.update(config=cfg, config_key=",".join(map(str, cfg)))
+            rows.append(row)
+    return rows
+
+
+def _pick(r):
+    keys = ("t_run_s", "p_median_w", "e_run_j", "e_run_counter_j", "gflops", "gflops_per_w", "sclk_act_mhz",
+            "temp_c", "window_s", "n_used")
+    return {"config": r["config"], **{k: r[k] for k in keys if k in r}}
+
+
+def summarize(sweep_rows, remeasure_rows=None, characterisation=None, workload=""):
+    """Time- and energy-optimal configs of a sweep (objective selection by
+    the library's gt_select), the same two re-measured with long windows when
+    available, the energy/time trade-off, and the Pareto front."""
+    t_opt, e_opt = optima(sweep_rows)
+    out = {"workload": workload, "configs_measured": len([r for r in sweep_rows if "error" not in r]),
+           "sweep_time_optimal": _pick(t_opt), "sweep_energy_optimal": _pick(e_opt)}
+    final = remeasure_rows if remeasure_rows else [r for r in sweep_rows if "error" not in r]
+    ft, fe = optima(final)
+    out["time_optimal"], out["energy_optimal"] = _pick(ft), _pick(fe)
+    out["efficiency_gain_energy_vs_time"] = fe["gflops_per_w"] / ft["gflops_per_w"]
+    out["speed_change_energy_vs_time_pct"] = gain_pct(ft["gflops"], fe["gflops"])
+    out["pareto_front"] = [{"config": r["config"], "gflops": r["gflops"], "gflops_per_w": r["gflops_per_w"]}
+                           for r in pareto(sweep_rows)]
+    if remeasure_rows:
+        out["remeasured"] = len(remeasure_rows)
+        ratios = [r["e_run_counter_j"] / r["e_run_j"] for r in remeasure_rows
+                  if r.get("e_run_counter_j") == r.get("e_run_counter_j") and r.get("e_run_counter_j")]
+        if ratios:
+            out["energy_counter_vs_median_ratio"] = {"min": min(ratios), "max": max(ratios)}
+    if characterisation:
+        out["sensor"] = {k: v for k, v in characterisation.items() if k != "trace"}
+    return nan_to_none(out)
+
+
+def _main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description="summarise a sweep log into the tuned-config store")
+    ap.add_argument("cmd", choices=["summarize"])
+    ap.add_argument("--sweep", required=True, help="JSONL sweep log")
+    ap.add_argument("--remeasure", default=None, help="JSON list of long-window re-measurements")
+    ap.add_argument("--sensor", default=None, help="sensor characterisation JSON")
+    ap.add_argument("--workload", default="")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--csv", default=None)
+    a = ap.parse_args(argv)
+    gt.init(0, gt.INIT_HOST_ONLY)
+    rows = [json.loads(ln) for ln in open(a.sweep)]
+    re = json.load(open(a.remeasure)) if a.remeasure else None
+    ch = json.load(open(a.sensor)) if a.sensor else None
+    s = summarize(rows, re, ch, a.workload)
+    with open(a.out, "w") as fh:
+        json.dump(s, fh, indent=1)
+    if a.csv:
+        write_sweep_csv(rows, a.csv)
+    gt.shutdown()
+
+
+if __name__ == "__main__":
+    _main()
