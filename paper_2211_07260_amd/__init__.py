@@ -391,11 +391,13 @@ class Batch:
         rc = _lib.gt_batch_pack(items, self.n, ctypes.byref(self.cfg), None, 0, ctypes.byref(nb), ctypes.byref(tt))
         if rc not in (GT_OK, GT_E_CAPACITY):
             _check(rc)
-        host = torch.empty(nb.value, dtype=torch.uint8)
-        _check(_lib.gt_batch_pack(items, self.n, ctypes.byref(self.cfg), ctypes.c_void_p(host.data_ptr()),
+        # pinned staging so the upload is asynchronous on the current stream;
+        # kept alive with the batch until the copy has certainly run
+        self._host = torch.empty(nb.value, dtype=torch.uint8, pin_memory=True)
+        _check(_lib.gt_batch_pack(items, self.n, ctypes.byref(self.cfg), ctypes.c_void_p(self._host.data_ptr()),
                                   nb.value, ctypes.byref(nb), ctypes.byref(tt)))
         self.total_tiles = tt.value
-        self.blob = host.to(convs[0][0].device)
+        self.blob = self._host.to(convs[0][0].device, non_blocking=True)
         self._keep = convs  # the device buffers must outlive the batch
 
     def run(self, grid_blocks=0, stream=None):

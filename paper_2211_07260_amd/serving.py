@@ -1,0 +1,249 @@
+"""Continuous-batching serving loop for a mix of convolution requests.
+
+Requests arrive over time (Poisson arrivals in the benchmark).  The loop
+admits waiting requests first-come first-served while a slot is free and the
+request's device footprint (input, filter, output) fits the memory budget;
+each admitted group is launched at once -- single-channel requests as one
+persistent batched launch per filter size, with the per-size autotuned
+config, multi-channel BF16 requests on the MFMA kernel -- on alternating
+compute streams, so new work is queued while earlier steps still run.  A
+step's requests complete when its event has fired; their memory and slots are
+then released and later arrivals are admitted.  Latency is completion minus
+arrival; energy per request is the serving window's energy (median power times
+window, and the energy counter) divided by the requests served.
+
+Payloads are synthetic and generated on the device at admission from the
+request's seed (no host staging), so a request's output can be recomputed
+alone for the equality check.
+"""
+import collections
+import math
+import time
+
+import paper_2211_07260_amd as gt
+from paper_2211_07260_amd import autotune
+
+
+class Request:
+    __slots__ = ("rid", "kind", "side", "f", "c", "t_arrive", "seed", "t_admit", "t_done", "bufs", "config",
+                 "bytes")
+
+    def __init__(self, rid, kind, side, f, c, t_arrive, seed):
+        self.rid, self.kind, self.side, self.f, self.c = rid, kind, side, f, c
+        self.t_arrive, self.seed = t_arrive, seed
+        self.t_admit = self.t_done = None
+        self.bufs = None
+        self.config = None
+        self.bytes = footprint(kind, side, f, c)
+
+    def flops(self):
+        if self.kind == "xcorr_f32":
+            return 2.0 * self.side * self.side * self.f * self.f
+        return 2.0 * self.side * self.side * self.c * self.c * self.f * self.f
+
+
+def footprint(kind, side, f, c):
+    """Device bytes of one request: input, filter and output."""
+    if kind == "xcorr_f32":
+        return 4 * ((side + f - 1) ** 2 + f * f + side * side)
+    return 2 * side * side * c + 2 * c * f * f * c + 4 * side * side * c
+
+
+def admit(waiting, mem_free, slots_free, max_batch):
+    """First-come first-served admission: take requests from the head of the
+    queue while a slot is free and the footprint fits; stop at the first that
+    does not fit (no overtaking, so no request starves).  Returns the count."""
+    n = 0
+    for r in waiting:
+        if n >= max_batch or slots_free <= 0 or r.bytes > mem_free:
+            break
+        mem_free -= r.bytes
+        slots_free -= 1
+        n += 1
+    return n
+
+
+def make_payload(r, device):
+    import torch
+    g = torch.Generator(device=device).manual_seed(r.seed)
+    if r.kind == "xcorr_f32":
+        img = torch.rand(r.side + r.f - 1, r.side + r.f - 1, generator=g, device=device)
+        w = torch.rand(r.f, r.f, generator=g, device=device)
+        out = torch.empty(r.side, r.side, device=device)
+    else:
+        img = torch.randn(1, r.side, r.side, r.c, generator=g, device=device).to(torch.bfloat16)
+        w = torch.randn(r.c, r.f, r.f, r.c, generator=g, device=device).to(torch.bfloat16)
+        out = torch.empty(1, r.side, r.side, r.c, device=device)
+    return img, w, out
+
+
+class Step:
+    __slots__ = ("reqs", "event", "batches")
+
+    def __init__(self, reqs, event, batches):
+        self.reqs, self.event, self.batches = reqs, event, batches
+
+
+class Engine:
+    def __init__(self, mem_budget=32 << 30, max_slots=512, max_batch=256, n_streams=2, store=None,
+                 keep_outputs=False, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.mem_budget, self.max_slots, self.max_batch = mem_budget, max_slots, max_batch
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
+        self.store = store if store is not None else autotune.load()
+        self.keep_outputs = keep_outputs
+        self.outputs = {}
+        self.mem_used = 0
+        self.peak_mem = 0
+        self.slots_used = 0
+        self.rejected = []
+
+    def _launch(self, reqs, stream):
+        torch = self.torch
+        with torch.cuda.stream(stream):
+            for r in reqs:
+                r.bufs = make_payload(r, self.device)
+            groups = collections.defaultdict(list)
+            batches = []
+            for r in reqs:
+                if r.kind == "xcorr_f32":
+                    groups[r.f].append(r)
+                else:
+                    img, w, out = r.bufs
+                    r.config = (64, 1, 1, 1, 0, 0)
+                    p = gt.conv_problem(gt.IGEMM_BF16_MFMA, 1, r.side, r.side, r.c, r.c, r.f, r.f)
+                    gt.conv2d_run(p, r.config, img, w, out, stream=stream)
+            for f, rs in groups.items():
+                # config of the group's typical size (work-weighted mean side)
+                side = math.sqrt(sum(r.side ** 2 for r in rs) / len(rs))
+                cfg = autotune.lookup(self.store, f, side)
+                for r in rs:
+                    r.config = cfg
+                b = gt.Batch([(r.bufs[0], r.bufs[1], r.bufs[2], r.side, r.side, f) for r in rs], cfg)
+                b.run(stream=stream)
+                batches.append(b)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        return Step(reqs, ev, batches)
+
+    def run(self, requests, realtime=True, poll_s=5e-5, progress=None):
+        """Serve requests (sorted by t_arrive, seconds from the start).  With
+        realtime=False every request is available at t = 0 (saturation)."""
+        torch = self.torch
+        pending = collections.deque(sorted(requests, key=lambda r: r.t_arrive))
+        waiting = collections.deque()
+        inflight = collections.deque()
+        done = []
+        k = 0
+        t0 = time.perf_counter()
+        while pending or waiting or inflight:
+            now = time.perf_counter() - t0
+            while pending and (not realtime or pending[0].t_arrive <= now):
+                waiting.append(pending.popleft())
+            while inflight and inflight[0].event.query():
+                st = inflight.popleft()
+                t = time.perf_counter() - t0
+                for r in st.reqs:
+                    r.t_done = t
+                    self.mem_used -= r.bytes
+                    self.slots_used -= 1
+                    if self.keep_outputs:
+                        self.outputs[r.rid] = r.bufs[2]
+                    r.bufs = None
+                    done.append(r)
+                if progress and len(done) // 500 != (len(done) - len(st.reqs)) // 500:
+                    progress("served %d" % len(done))
+            while waiting and waiting[0].bytes > self.mem_budget:  # can never fit: reject
+                self.rejected.append(waiting.popleft())
+            n = admit(waiting, self.mem_budget - self.mem_used, self.max_slots - self.slots_used, self.max_batch)
+            if n:
+                reqs = [waiting.popleft() for _ in range(n)]
+                t = time.perf_counter() - t0
+                for r in reqs:
+                    r.t_admit = t
+                    self.mem_used += r.bytes
+                    self.slots_used += 1
+                self.peak_mem = max(self.peak_mem, self.mem_used)
+                inflight.append(self._launch(reqs, self.streams[k % len(self.streams)]))
+                k += 1
+                continue
+            if not inflight and not waiting and pending and realtime:
+                time.sleep(max(0.0, min(pending[0].t_arrive - (time.perf_counter() - t0), 1e-3)))
+            else:
+                time.sleep(poll_s)
+        torch.cuda.synchronize()
+        return done
+
+
+def requests_from_mix(mix, rate_scale=1.0, seed_base=1000):
+    """Request objects from synthetic.serving_requests dicts; arrival times are
+    multiplied by rate_scale (rate_scale < 1 compresses time)."""
+    return [Request(i, m["kind"], m["side"], m["f"], m["c"], m["t_arrive"] * rate_scale, seed_base + i)
+            for i, m in enumerate(mix)]
+
+
+def latency_stats(done):
+    lat = sorted((r.t_done - r.t_arrive) * 1e3 for r in done)
+    if not lat:
+        return {}
+
+    def pct(p):
+        return lat[min(len(lat) - 1, max(0, int(math.ceil(p / 100.0 * len(lat))) - 1))]
+    return {"n": len(lat), "p50_ms": pct(50), "p99_ms": pct(99), "mean_ms": sum(lat) / len(lat),
+            "max_ms": lat[-1]}
+
+
+def energy_stats(samples, t_start, t_stop, n_req):
+    """Serving-window energy from sampler readings (host time t_s)."""
+    kept = [s for s in samples if t_start <= s["t_s"] <= t_stop]
+    if not kept:
+        return {}
+    p = sorted(s["power_w"] for s in kept)
+    med = p[len(p) // 2] if len(p) % 2 else 0.5 * (p[len(p) // 2 - 1] + p[len(p) // 2])
+    win = t_stop - t_start
+    out = {"window_s": win, "p_median_w": med, "j_per_request": med * win / n_req}
+    upd = [(s["energy_t_s"], s["energy_j"]) for i, s in enumerate(kept)
+           if i > 0 and s["energy_t_s"] != kept[i - 1]["energy_t_s"]]
+    if len(upd) >= 2 and upd[-1][0] > upd[0][0]:
+        p_ctr = (upd[-1][1] - upd[0][1]) / (upd[-1][0] - upd[0][0])
+        out["j_per_request_counter"] = p_ctr * win / n_req
+        out["p_counter_w"] = p_ctr
+    return out
+
+
+def benchmark(n_req=2000, seed=0, util=0.7, mem_budget=64 << 30, progress=print):
+    """The serving-mix benchmark: saturation throughput with every request
+    queued at t = 0, then Poisson arrivals at util x that rate.  Returns a
+    report dict (latency percentiles, throughput, energy per request)."""
+    import torch
+    from synthetic import serving_requests
+    mix = serving_requests(n_req, 1.0, seed=seed)
+    # saturation
+    eng = Engine(mem_budget=mem_budget)
+    reqs = requests_from_mix(mix)
+    t0 = time.perf_counter()
+    done = eng.run(reqs, realtime=False)
+    t_sat = time.perf_counter() - t0
+    mu = len(done) / t_sat
+    progress("saturation: %d requests in %.3f s (%.1f req/s)" % (len(done), t_sat, mu))
+    lam = util * mu
+    reqs = requests_from_mix(mix, rate_scale=1.0 / lam)
+    eng = Engine(mem_budget=mem_budget)
+    gt.sampler_start(2.0)
+    t_start = gt.sensor_read()["t_s"]
+    t0 = time.perf_counter()
+    done = eng.run(reqs, realtime=True)
+    wall = time.perf_counter() - t0
+    t_stop = gt.sensor_read()["t_s"]
+    samples = gt.sampler_stop()
+    torch.cuda.synchronize()
+    flops = sum(r.flops() for r in done)
+    rep = {"requests": len(done), "arrival_rate_hz": lam, "saturation_rate_hz": mu, "util_target": util,
+           "wall_s": wall, "throughput_rps": len(done) / wall, "tflops_delivered": flops / wall / 1e12,
+           "peak_admitted_bytes": eng.peak_mem, "mem_budget_bytes": mem_budget,
+           "mix": {"xcorr_f32": sum(r.kind == "xcorr_f32" for r in done),
+                   "conv_bf16": sum(r.kind == "conv_bf16" for r in done)}}
+    rep.update(latency=latency_stats(done), energy=energy_stats(samples, t_start, t_stop, len(done)))
+    return rep
