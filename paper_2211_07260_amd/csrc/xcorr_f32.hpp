@@ -254,9 +254,24 @@ __device__ __forceinline__ void xcorr_tile_direct(const XcorrArgs &a, int x0, in
     }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (linear id mod 8),
+// each XCD with its own L2.  Remap so that XCD k processes the k-th eighth of
+// the tiles in row-major order: horizontally adjacent tiles, which share
+// fw-1 halo columns, then run on the same XCD and share its L2.
+__device__ __forceinline__ void xcd_tile(int &tx, int &ty) {
+    const int gx = gridDim.x, n = gx * gridDim.y;
+    const int lin = blockIdx.y * gx + blockIdx.x;
+    int t = lin;
+    if ((n & 7) == 0) t = (lin & 7) * (n >> 3) + (lin >> 3);
+    ty = t / gx;
+    tx = t - ty * gx;
+}
+
 template <int TX, int TY, int FW, int RP>
 __global__ __launch_bounds__(1024) void xcorr_f32_kernel(XcorrArgs a) {
-    const int x0 = blockIdx.x * blockDim.x * TX, y0 = blockIdx.y * blockDim.y * TY;
+    int tx, ty;
+    xcd_tile(tx, ty);
+    const int x0 = tx * blockDim.x * TX, y0 = ty * blockDim.y * TY;
     if constexpr (RP == 0) {
         extern __shared__ __align__(16) float lds[];
         xcorr_tile_lds<TX, TY, FW>(a, x0, y0, lds);
