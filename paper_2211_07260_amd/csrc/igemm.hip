@@ -228,6 +228,118 @@ __global__ __launch_bounds__(256) void igemm_bf16_mfma_any_kernel(IgemmArgs a, i
         }
 }
 
+// LDS-staged variant.  A workgroup owns a 4-row x 64-column output tile
+// (one row per wave, four 16-pixel M-tiles per wave) for 16*NT output
+// channels.  Its input halo, (4+R-1) x (64+S-1) pixels x C channels, is
+// staged in LDS once (zero where the filter overhangs the image), so each
+// input byte crosses L2 once per workgroup instead of once per filter tap.
+// LDS holds pixel-major 16-byte channel chunks; chunk q of halo column hx is
+// stored at slot q ^ swz(hx), which spreads the 16 lanes of an A-fragment read
+// (16 consecutive pixels, same chunk) over distinct banks.  Weights (B) are
+// read from L2 as 16-byte fragments; the (s, c-block) walk of one filter row
+// is fully unrolled so the compiler can hoist those loads.
+constexpr int kLdsTH = 4, kLdsTW = 64;
+
+template <int C>
+__device__ __forceinline__ int lds_swz(int hx) {
+    if constexpr (C == 64)
+        return (hx >> 1) & 7;
+    else
+        return (hx >> 2) & 3;
+}
+
+template <int C>
+constexpr int lds_bytes_for(int R, int S) {
+    return (kLdsTH + R - 1) * (kLdsTW + S - 1) * C * 2;
+}
+
+template <int C, int NT, int R, int S>
+__global__ __launch_bounds__(256) void igemm_bf16_lds_kernel(IgemmArgs a) {
+    constexpr int CH = C / 8, KC = C / 32;
+    constexpr int HW = kLdsTW + S - 1, HH = kLdsTH + R - 1;
+    constexpr int NCHUNK = HH * HW * CH;
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int tiles_x = (a.out_w + kLdsTW - 1) / kLdsTW, tiles_y = (a.out_h + kLdsTH - 1) / kLdsTH;
+    int t = blockIdx.x;
+    const int txi = t % tiles_x;
+    t /= tiles_x;
+    const int tyi = t % tiles_y, b = t / tiles_y;
+    const int x0 = txi * kLdsTW, y0 = tyi * kLdsTH;
+    const int n_blk = blockIdx.y * (16 * NT);
+    const unsigned short *in = static_cast<const unsigned short *>(a.in);
+    const unsigned short *wt = static_cast<const unsigned short *>(a.w);
+
+    // stage the halo: chunk k = (pixel p = k / CH, channel chunk q = k % CH)
+    for (int k = threadIdx.x; k < NCHUNK; k += 256) {
+        const int p = k / CH, q = k - p * CH;
+        const int hy = p / HW, hx = p - hy * HW;
+        const int y = y0 - a.ph + hy, x = x0 - a.pw + hx;
+        u32x4 v = u32x4{0u, 0u, 0u, 0u};
+        if (y >= 0 && y < a.h && x >= 0 && x < a.wd)
+            v = *reinterpret_cast<const u32x4 *>(in + (((size_t)b * a.h + y) * a.wd + x) * C + q * 8);
+        *reinterpret_cast<u32x4 *>(lds + p * (C * 2) + 16 * (q ^ lds_swz<C>(hx))) = v;
+    }
+    __syncthreads();
+
+    f32x4 acc[kMT][NT];
+#pragma unroll
+    for (int m = 0; m < kMT; ++m)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    auto filter_row = [&](int r) {
+        const unsigned char *row = lds + (wave + r) * HW * (C * 2);
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                const int q = kc * 4 + lg;
+                u32x4 B[NT], A[kMT];
+#pragma unroll
+                for (int j = 0; j < NT; ++j) {
+                    const int co = n_blk + j * 16 + li;
+                    B[j] = *reinterpret_cast<const u32x4 *>(wt + (((size_t)co * R + r) * S + s) * C + q * 8);
+                }
+#pragma unroll
+                for (int m = 0; m < kMT; ++m) {
+                    const int hx = m * 16 + li + s;
+                    A[m] = *reinterpret_cast<const u32x4 *>(row + hx * (C * 2) + 16 * (q ^ lds_swz<C>(hx)));
+                }
+#pragma unroll
+                for (int m = 0; m < kMT; ++m)
+#pragma unroll
+                    for (int j = 0; j < NT; ++j)
+                        acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            __builtin_bit_cast(bf16x8, A[m]), __builtin_bit_cast(bf16x8, B[j]), acc[m][j], 0, 0, 0);
+            }
+    };
+    if constexpr (R <= 7) {  // small filters: the whole walk unrolled (no loop-carried accumulator copies)
+#pragma unroll
+        for (int r = 0; r < R; ++r) filter_row(r);
+    } else {
+#pragma unroll 1
+        for (int r = 0; r < R; ++r) filter_row(r);
+    }
+
+    // D[m = 4*lg + e][n = li] of M-tile m: pixel (y0 + wave, x0 + 16*m + 4*lg + e)
+    const int y = y0 + wave;
+    if (y < a.out_h) {
+#pragma unroll
+        for (int m = 0; m < kMT; ++m)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int x = x0 + m * 16 + lg * 4 + e;
+                if (x < a.out_w) {
+                    float *dst = a.out + (((size_t)b * a.out_h + y) * a.out_w + x) * a.c_out + n_blk + li;
+#pragma unroll
+                    for (int j = 0; j < NT; ++j) dst[j * 16] = acc[m][j][e];
+                }
+            }
+    }
+}
+
 constexpr int kValuP = 8, kValuWaves = 4;  // pixels per wave, waves per workgroup
 
 // A wave computes kValuP consecutive output pixels of one output row (all
@@ -351,6 +463,29 @@ const void *valu_kernel_for(int f, int c) {
     }
 }
 
+struct LdsEntry {
+    int c, nt, f;
+    const void *fn;
+    int lds;
+};
+#define GT_L(C, NT, F) {C, NT, F, (const void *)&igemm_bf16_lds_kernel<C, NT, F, F>, lds_bytes_for<C>(F, F)}
+const LdsEntry kLdsTable[] = {
+    GT_L(64, 4, 1), GT_L(64, 4, 3), GT_L(64, 4, 5), GT_L(64, 4, 7), GT_L(64, 4, 9),
+    GT_L(64, 2, 1), GT_L(64, 2, 3), GT_L(64, 2, 5), GT_L(64, 2, 7), GT_L(64, 2, 9),
+    GT_L(32, 4, 1), GT_L(32, 4, 3), GT_L(32, 4, 5), GT_L(32, 4, 7), GT_L(32, 4, 9), GT_L(32, 4, 17),
+    GT_L(32, 2, 1), GT_L(32, 2, 3), GT_L(32, 2, 5), GT_L(32, 2, 7), GT_L(32, 2, 9), GT_L(32, 2, 17),
+};
+#undef GT_L
+
+// The LDS-staged kernel for (c_in, c_out, f) when instantiated and its halo
+// fits the device's LDS; null otherwise.
+const LdsEntry *lds_kernel_for(int f, int c, int c_out) {
+    const int nt = (c_out % 64 == 0) ? 4 : 2;
+    for (const LdsEntry &e : kLdsTable)
+        if (e.c == c && e.nt == nt && e.f == f && e.lds <= state().dev.lds_per_block) return &e;
+    return nullptr;
+}
+
 }  // namespace
 
 int validate_igemm(const gt_problem &p, const gt_conv_config &) {
@@ -395,6 +530,16 @@ int launch_igemm(const gt_problem &p, const gt_conv_config &, const void *in, co
     a.pw = p.pad_w;
     a.m_total = p.n * p.out_h * p.out_w;
     void *args[] = {&a};
+    if (p.kind == GT_IGEMM_BF16_MFMA && p.filt_h == p.filt_w) {
+        if (const LdsEntry *e = lds_kernel_for(p.filt_h, p.c_in, p.c_out)) {
+            const int64_t tiles = (int64_t)p.n * ((p.out_h + kLdsTH - 1) / kLdsTH) * ((p.out_w + kLdsTW - 1) / kLdsTW);
+            if (e->lds > 65536)
+                GT_HIP_CHECK(hipFuncSetAttribute(e->fn, hipFuncAttributeMaxDynamicSharedMemorySize, e->lds));
+            dim3 grid((unsigned)tiles, (unsigned)(p.c_out / (16 * e->nt)));
+            GT_HIP_CHECK(hipLaunchKernel(e->fn, grid, dim3(256), args, (size_t)e->lds, s));
+            return GT_OK;
+        }
+    }
     if (p.kind == GT_IGEMM_BF16_MFMA) {
         const int nt = (p.c_out % 64 == 0) ? 4 : 2;
         const int per_wg = kMfmaWaves * kMT * 16;
