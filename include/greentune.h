@@ -201,11 +201,17 @@ int fit_power_model(const double *f_mhz, const double *p_w, const double *v_or_n
 
 /* ---- helpers of the method ---- */
 
-/* P*(f) of a fitted model (Eq. 2/3); NaN on a null model. */
+/* P*(f) of a fitted model (Eq. 2/3); NaN on a null model.  For a model
+ * fitted with measured voltage, v is taken as 1 (the fit, not the curve, is
+ * what that variant provides). */
 double gt_power_model_eval(const gt_power_model *model, double f_mhz);
-/* Model-optimal clock: argmin over settable[0..n) of P*(f)/f (the energy
- * estimate of section V.D); ties (relative gap <= 1e-12) go to the higher
- * clock.  Then the band: the settable clocks within [(1-rel_half) f_opt,
+/* Throttling clock: where the unclipped model p_idle + alpha f v(f)^2 reaches
+ * p_max (bisection); +inf if it never does below 1e7 MHz. */
+double gt_power_model_throttle_clock(const gt_power_model *model);
+/* Model-optimal clock: argmin over settable[0..n) of the energy estimate of
+ * section V.D, P*(f)/f, with performance linear in the clock only up to the
+ * throttling clock (Fig. 8): E*(f) = P*(f_e)/f_e, f_e = min(f, f_thr).  Ties
+ * (relative gap <= 1e-12) go to the higher clock.  Then the band: the settable clocks within [(1-rel_half) f_opt,
  * (1+rel_half) f_opt], ascending (rel_half = 0.1 in the paper).
  * GT_E_CAPACITY if cap is too small (*n_band still written). */
 int gt_power_model_band(const gt_power_model *model, const double *settable, size_t n,

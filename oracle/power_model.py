@@ -17,9 +17,11 @@ below tau and grows with slope beta above it:
 
 ``literal=True`` evaluates the printed form instead.
 
-Energy per run is estimated as E*(f) proportional to P*(f)/f (the paper's
-"absolute power divided by clock frequency", which assumes run time scales
-as 1/f); the model-optimal clock is its argmin over the settable clocks,
+Energy per run is estimated as E*(f) proportional to P*(f)/f (absolute
+power divided by clock frequency, run time scaling as 1/f), with the clock
+capped at the throttling point where the model reaches P_max (the paper
+estimates performance as linear in the clock up to where throttling occurs);
+the model-optimal clock is its argmin over the settable clocks,
 ties going to the highest clock (faster at equal energy); the tuning band is
 the settable clocks within +-10 % of that optimum.
 
@@ -51,18 +53,45 @@ def power(f, p_idle, alpha, beta, tau, p_max, v=None, literal=False):
     return np.minimum(p_max, p_idle + alpha * f * vv * vv)
 
 
-def energy_estimate(f, model):
-    """E*(f) proportional to P*(f)/f."""
+def throttle_clock(model, f_hi=1e7):
+    """Clock at which the unclipped model reaches P_max: above it the device
+    cannot hold the clock (the clipped part of Eq. 2).  The unclipped curve
+    P_idle + alpha f v(f)^2 is increasing, so the crossing is found by
+    bisection; inf when it never reaches P_max below f_hi."""
+    def g(f):
+        v = float(voltage(f, model["beta"], model["tau"], model.get("literal", False)))
+        return model["p_idle"] + model["alpha"] * f * v * v - model["p_max"]
+    if g(f_hi) <= 0:
+        return float("inf")
+    lo, hi = 0.0, f_hi
+    if g(lo) > 0:
+        return 0.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if g(mid) <= 0:
+            lo = mid
+        else:
+            hi = mid
+    return lo
+
+
+def energy_estimate(f, model, f_thr=None):
+    """E*(f) proportional to P*(f)/f, with performance linear in the clock
+    only up to the throttling clock f_thr (the paper's performance estimate,
+    Fig. 8): above it the device runs at f_thr and P_max, so
+    E*(f) = P*(min(f, f_thr)) / min(f, f_thr)."""
     f = np.asarray(f, dtype=np.float64)
-    return power(f, model["p_idle"], model["alpha"], model["beta"], model["tau"],
-                 model["p_max"]) / f
+    f_eff = np.minimum(f, throttle_clock(model) if f_thr is None else f_thr)
+    return power(f_eff, model["p_idle"], model["alpha"], model["beta"], model["tau"],
+                 model["p_max"]) / f_eff
 
 
 def optimal_clock(settable, model):
     """argmin over the settable clocks of E*(f); ties -> highest clock."""
     best_f, best_e = None, None
+    f_thr = throttle_clock(model)
     for f in sorted(float(x) for x in settable):
-        e = float(energy_estimate(f, model))
+        e = float(energy_estimate(f, model, f_thr))
         if best_e is None or e <= best_e * (1.0 + TIE_REL):
             if best_e is None or e < best_e:
                 best_e = e

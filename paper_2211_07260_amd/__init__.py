@@ -129,6 +129,7 @@ def _load():
                                  P(Measurement)], c_int),
         "fit_power_model": ([P(c_double), P(c_double), P(c_double), c_size, c_double, P(PowerModel)], c_int),
         "gt_power_model_eval": ([P(PowerModel), c_double], c_double),
+        "gt_power_model_throttle_clock": ([P(PowerModel)], c_double),
         "gt_power_model_band": ([P(PowerModel), P(c_double), c_size, c_double, P(c_double), P(c_double),
                                  c_size, P(c_size)], c_int),
         "gt_energy_from_samples": ([P(c_double), P(c_double), c_size, c_double, c_double, ctypes.c_int64,
@@ -162,7 +163,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("gt_init", "gt_shutdown", "gt_last_error", "gt_version", "conv2d_run",
-            "tune_space_enumerate", "measure_time_energy", "fit_power_model", "gt_power_model_eval",
+            "tune_space_enumerate", "measure_time_energy", "fit_power_model", "gt_power_model_eval", "gt_power_model_throttle_clock",
             "gt_power_model_band", "gt_energy_from_samples", "gt_select", "gt_problem_flops",
             "gt_conv_lds_bytes", "gt_sensor_read", "gt_settable_clocks", "gt_dvfs_state",
             "gt_fake_sensor_model", "gt_roofline_probe", "gt_batch_pack", "conv2d_run_batched",
@@ -287,6 +288,10 @@ def fit_power_model(f_mhz, p_w, p_max, v=None, literal=False):
 
 def power_model_eval(model, f_mhz):
     return _lib.gt_power_model_eval(ctypes.byref(model), float(f_mhz))
+
+
+def power_model_throttle_clock(model):
+    return _lib.gt_power_model_throttle_clock(ctypes.byref(model))
 
 
 def power_model_band(model, settable, rel_half=0.1):

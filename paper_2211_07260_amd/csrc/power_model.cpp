@@ -284,6 +284,28 @@ double gt_power_model_eval(const gt_power_model *m, double f_mhz) {
     return std::min(m->p_max, m->p_idle + m->alpha * f_mhz * v * v);
 }
 
+double gt_power_model_throttle_clock(const gt_power_model *m) {
+    if (!m) return NAN;
+    // the unclipped curve p_idle + alpha f v(f)^2 is non-decreasing in f
+    auto g = [m](double f) {
+        double v = 1.0;
+        if (!m->v_measured && f >= m->tau_mhz)
+            v = m->literal_eq3 ? m->beta * (f - m->tau_mhz) : 1.0 + m->beta * (f - m->tau_mhz);
+        return m->p_idle + m->alpha * f * v * v - m->p_max;
+    };
+    double lo = 0.0, hi = 1e7;
+    if (g(hi) <= 0) return INFINITY;
+    if (g(lo) > 0) return 0.0;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (g(mid) <= 0)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 int gt_power_model_band(const gt_power_model *m, const double *settable, size_t n, double rel_half,
                         double *f_opt, double *band, size_t cap, size_t *n_band) {
     clear_error();
@@ -292,10 +314,17 @@ int gt_power_model_band(const gt_power_model *m, const double *settable, size_t 
     std::vector<double> s(settable, settable + n);
     std::sort(s.begin(), s.end());
     if (!(s[0] > 0)) return set_error(GT_E_INVAL, "gt_power_model_band: clocks must be positive");
-    // energy estimate E*(f) = P*(f)/f; ascending scan so ties end on the higher clock
-    double best_f = s[0], best_e = gt_power_model_eval(m, s[0]) / s[0];
+    // energy estimate E*(f) = P*(f_e)/f_e with f_e = min(f, throttling clock):
+    // above the throttling clock the device runs at that clock and P_max.
+    // Ascending scan so ties end on the higher clock.
+    const double f_thr = gt_power_model_throttle_clock(m);
+    auto energy = [&](double f) {
+        const double fe = std::min(f, f_thr);
+        return gt_power_model_eval(m, fe) / fe;
+    };
+    double best_f = s[0], best_e = energy(s[0]);
     for (size_t i = 1; i < n; ++i) {
-        const double e = gt_power_model_eval(m, s[i]) / s[i];
+        const double e = energy(s[i]);
         if (e <= best_e * (1.0 + 1e-12)) {
             if (e < best_e) best_e = e;
             best_f = s[i];

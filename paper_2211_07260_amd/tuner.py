@@ -174,21 +174,33 @@ def fit_clocks(settable, n=5):
 
 
 def steered_search(measure, configs, settable, p_max, n_fit=5, rel_half=0.1, fit_config=None):
-    """The paper's procedure: fit Eq. 2/3 to <= n_fit power readings of one
-    fully-loading config at uniformly spaced clocks, take the clock minimising
-    P*(f)/f, and measure the candidate configs only at the settable clocks
-    within +-rel_half of it.
+    """The paper's procedure (section V.D): fit Eq. 2/3 to <= n_fit power
+    readings of one fully-loading config, take the clock minimising P*(f)/f,
+    and measure the candidate configs only at the settable clocks within
+    +-rel_half of it.
+
+    The model is fitted up to the highest clock before throttling, so the
+    first reading is taken at the top clock: if the device throttles there,
+    the remaining readings are spread uniformly below the clock it sustained
+    instead of over the whole range.  Throttled readings are not fitted.
 
     measure(config, clock_mhz) -> dict with t_run_s, e_run_j, p_median_w,
     sclk_act_mhz, throttled.  Returns a report dict."""
     fit_config = fit_config or configs[0]
-    fit_pts = []
-    for f in fit_clocks(settable, n_fit):
-        m = measure(fit_config, f)
-        fit_pts.append({"clock_mhz": f, **m})
+    s = sorted(settable)
+    top = measure(fit_config, s[-1])
+    fit_pts = [{"clock_mhz": s[-1], **top}]
+    f_hi = s[-1]
+    if top.get("throttled"):
+        below = [f for f in s if f <= top.get("sclk_act_mhz", s[-1])]
+        f_hi = below[-1] if below else s[0]
+    for f in fit_clocks([f for f in s if f <= f_hi], n_fit - 1 if top.get("throttled") else n_fit):
+        if f == s[-1]:
+            continue
+        fit_pts.append({"clock_mhz": f, **measure(fit_config, f)})
     use = [p for p in fit_pts if not p.get("throttled")]
     model = gt.fit_power_model([p["clock_mhz"] for p in use], [p["p_median_w"] for p in use], p_max)
-    f_opt, band = gt.power_model_band(model, settable, rel_half)
+    f_opt, band = gt.power_model_band(model, s, rel_half)
     rows = []
     for cfg in configs:
         for f in band:

@@ -151,7 +151,16 @@ def test_eval_matches_oracle(m):
         assert gt.power_model_eval(lit, f) == pytest.approx(want, rel=1e-15)
 
 
+@pytest.mark.parametrize("m", MODELS)
+def test_throttle_clock_matches_oracle(m):
+    pmod = gt.power_model(m["p_idle"], m["alpha"], m["beta"], m["tau"], m["p_max"])
+    want = opm.throttle_clock(dict(m))
+    got = gt.power_model_throttle_clock(pmod)
+    assert got == want or got == pytest.approx(want, rel=1e-12)
+
+
 @pytest.mark.parametrize("m", MODELS + [dict(p_idle=0.0, alpha=0.5, beta=0.01, tau=1200.0, p_max=1e9),
+                                       dict(p_idle=320.0, alpha=0.37, beta=0.00115, tau=1020.0, p_max=1400.0),
                                        dict(p_idle=300.0, alpha=0.1, beta=0.0, tau=1000.0, p_max=1e9)])
 @pytest.mark.parametrize("step", [100.0, 25.0, 5.0])
 def test_band_matches_oracle(m, step):

@@ -66,10 +66,32 @@ def test_flat_tie_goes_to_highest_clock():
     assert pm.optimal_clock(settable, m) == 1200.0
 
 
-def test_clipping_region_is_p_max_over_f():
-    f = np.array([2300.0, 2400.0])
-    e = pm.energy_estimate(f, M)
-    np.testing.assert_allclose(e, 2000.0 / f, rtol=1e-15)
+def test_throttle_clock_closed_form():
+    # M: 100 + 0.2 f (1 + 0.001 (f - 1000))^2 = 2000 above tau.  With u = f/1000:
+    # 0.2*1000 u (u)^2 = 1900 -> u^3 = 9.5 -> f = 1000 * 9.5^(1/3)
+    f_thr = pm.throttle_clock(M)
+    assert f_thr == pytest.approx(1000.0 * 9.5 ** (1.0 / 3.0), rel=1e-12)
+    assert pm.throttle_clock(dict(M, beta=0.0, p_max=1e12)) == float("inf")
+
+
+def test_clipping_region_energy_is_flat_at_throttle():
+    # above the throttling clock the device runs at f_thr and P_max
+    f_thr = pm.throttle_clock(M)
+    e = pm.energy_estimate(np.array([2300.0, 2400.0, f_thr]), M)
+    np.testing.assert_allclose(e, 2000.0 / f_thr, rtol=1e-12)
+
+
+def test_optimum_never_above_throttle():
+    # a cheap top clock under the clip must not look optimal: P_max / f would
+    # decrease past f_thr if the clock were assumed to hold
+    m = dict(p_idle=320.0, alpha=0.37, beta=0.00115, tau=1020.0, p_max=1400.0)
+    settable = np.arange(500.0, 2401.0, 10.0)
+    f_opt = pm.optimal_clock(settable, m)
+    assert f_opt <= pm.throttle_clock(m)
+    # and it is the interior stationary point found on a fine grid
+    grid = np.arange(500.0, 2400.0, 0.5)
+    e = pm.energy_estimate(grid, m)
+    assert abs(f_opt - grid[np.argmin(e)]) <= 10.0
 
 
 def test_band_closed_form():
