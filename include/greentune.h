@@ -296,6 +296,19 @@ int gt_graph_end(void *hip_stream, void **graph_exec);
 int gt_graph_launch(void *graph_exec, void *hip_stream);
 int gt_graph_destroy(void *graph_exec);
 
+/* ---- search difficulty (section V.B) ---- */
+
+/* Fitness flow graph of a measured tune space: neighbours differ in exactly
+ * one tunable, edges point to strictly better (lower) fitness.  PageRank with
+ * the given damping (0.85 usual), uniform teleportation, rank of nodes without
+ * out-edges spread uniformly.  Writes pagerank[n] and is_minimum[n] when non-
+ * null, and for each p_values[k] the proportion of centrality: PageRank mass of
+ * the minima with fitness <= p * min(fitness) over the mass of all minima.
+ * Host-only.  Errors: GT_E_INVAL. */
+int gt_ffg_centrality(const gt_conv_config *cfgs, const double *fitness, size_t n, double damping,
+                      const double *p_values, size_t n_p, double *pagerank, int32_t *is_minimum,
+                      double *proportion);
+
 /* ---- roofline probes ---- */
 
 /* Measure the achievable FP32 vector FMA rate (FMA with one SGPR operand, the

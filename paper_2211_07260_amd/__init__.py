@@ -153,6 +153,8 @@ def _load():
         "gt_sampler_start": ([c_double], c_int),
         "gt_sampler_stop": ([P(SensorSample), c_size, P(c_size)], c_int),
         "gt_sensor_busy": ([c_int], c_int),
+        "gt_ffg_centrality": ([P(ConvConfig), P(c_double), c_size, c_double, P(c_double), c_size, P(c_double),
+                               P(ctypes.c_int32), P(c_double)], c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -168,7 +170,7 @@ EXPORTED = ("gt_init", "gt_shutdown", "gt_last_error", "gt_version", "conv2d_run
             "gt_conv_lds_bytes", "gt_sensor_read", "gt_settable_clocks", "gt_dvfs_state",
             "gt_fake_sensor_model", "gt_roofline_probe", "gt_batch_pack", "conv2d_run_batched",
             "gt_graph_begin", "gt_graph_end", "gt_graph_launch", "gt_graph_destroy", "gt_sampler_start",
-            "gt_sampler_stop", "gt_sensor_busy")
+            "gt_sampler_stop", "gt_sensor_busy", "gt_ffg_centrality")
 
 
 def lib():
@@ -456,3 +458,19 @@ def sampler_stop(capacity=1 << 20):
 
 def sensor_busy(busy):
     _check(_lib.gt_sensor_busy(1 if busy else 0))
+
+
+# ---- search difficulty ----
+
+def ffg_centrality(configs, fitness, p_values=(1.0, 1.05, 1.1, 1.25, 1.5, 2.0), damping=0.85):
+    """PageRank over the fitness flow graph and the proportion of centrality
+    per p.  Returns (pagerank list, is_minimum list, proportions list)."""
+    n = len(configs)
+    cf = (ConvConfig * n)(*[as_config(c) for c in configs])
+    fa, _ = _darr(fitness)
+    pa, npv = _darr(p_values)
+    pr = (ctypes.c_double * n)()
+    im = (ctypes.c_int32 * n)()
+    prop = (ctypes.c_double * max(npv, 1))()
+    _check(_lib.gt_ffg_centrality(cf, fa, n, damping, pa, npv, pr, im, prop))
+    return list(pr), list(im), [prop[k] for k in range(npv)]

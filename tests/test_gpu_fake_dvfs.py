@@ -1,0 +1,74 @@
+"""The measurement loop with the DVFS knob and the power sensor replaced by
+the library's fake backends (the hardware clock is never touched): real
+kernel launches and HIP-event timing, synthetic power from a known Eq. 2/3
+model at the requested clock.  Checks the median-power energy arithmetic,
+the clock bookkeeping, the fit recovering the model from <= 5 readings, and
+that without the fake backend a clock request is refused."""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2211_07260_amd as g
+    yield g
+
+
+def bufs(f=17, side=1024):
+    dev = torch.device("cuda:0")
+    img = torch.rand(side + f - 1, side + f - 1, device=dev)
+    w = torch.rand(f, f, device=dev)
+    return img, w, torch.empty(side, side, device=dev)
+
+
+MODEL = dict(p_idle=240.0, alpha=0.35, beta=0.0012, tau=1250.0, p_max=5000.0)  # no clipping in range
+
+
+def test_clock_request_refused_without_permission(gt):
+    gt.init(0, 0)
+    try:
+        img, w, out = bufs()
+        with pytest.raises(gt.GreentuneError) as e:
+            gt.conv2d_run(gt.xcorr_problem(1024, 1024, 17, 17), (32, 8, 4, 2, 0, 0), img, w, out,
+                          clk=gt.clock(gt.CLOCK_SCLK_MHZ, 1500))
+        assert e.value.code == gt.GT_E_PERM
+        assert gt.dvfs_state() == (False, (0, 0))
+    finally:
+        gt.shutdown()
+
+
+def test_fake_measurement_and_steered_fit(gt):
+    from paper_2211_07260_amd import tuner
+    gt.init(0, gt.INIT_FAKE_SENSOR | gt.INIT_FAKE_DVFS)
+    try:
+        m = gt.power_model(MODEL["p_idle"], MODEL["alpha"], MODEL["beta"], MODEL["tau"], MODEL["p_max"])
+        gt.fake_sensor_model(m, noise_w=0.0)
+        img, w, out = bufs()
+        prob = gt.xcorr_problem(1024, 1024, 17, 17)
+        cfg = (32, 8, 4, 2, 0, 0)
+        for f in (800, 1300, 1900):
+            r = gt.measure_time_energy(prob, cfg, img, w, out, gt.clock(gt.CLOCK_SCLK_MHZ, f), window_s=0.15,
+                                       discard_s=0.03)
+            want = gt.power_model_eval(m, f)
+            assert r["p_median_w"] == pytest.approx(want, rel=1e-12)
+            assert r["e_run_j"] == pytest.approx(want * r["t_run_s"], rel=1e-12)
+            assert r["sclk_req_mhz"] == f and r["flags"] == 3 and r["launches"] >= 10
+            assert gt.dvfs_state() == (True, (gt.CLOCK_SCLK_MHZ, f))
+
+        def measure(c, f):
+            return gt.measure_time_energy(prob, c, img, w, out, gt.clock(gt.CLOCK_SCLK_MHZ, int(f)),
+                                          window_s=0.1, discard_s=0.02)
+        settable = gt.settable_clocks(100.0)
+        rep = tuner.steered_search(measure, [cfg], settable, p_max=MODEL["p_max"], n_fit=5)
+        assert len(rep["fit_points"]) <= 5
+        fit = rep["model"]
+        assert fit["rss"] < 1e-6
+        assert fit["alpha"] == pytest.approx(MODEL["alpha"], rel=1e-4)
+        assert rep["band_mhz"] and len(rep["band_mhz"]) < len(settable)
+    finally:
+        gt.shutdown()
