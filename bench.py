@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--config", type=str, default=None, help="bx,by,tx,ty,pad,rp")
     ap.add_argument("--probe", action="store_true", help="run the roofline probes only")
     ap.add_argument("--no-extras", action="store_true", help="skip the multi-channel timings")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix run")
+    ap.add_argument("--serving-requests", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the tuning method and its kernels run on a single "
@@ -167,6 +169,17 @@ def main():
     if not args.no_extras:
         extras = igemm_extras(gt, torch, dev)
 
+    serving_rep = None
+    if not args.no_serving:
+        from paper_2211_07260_amd import serving
+        del d_in, d_w, out
+        torch.cuda.empty_cache()
+        serving_rep = serving.benchmark(n_req=args.serving_requests,
+                                        progress=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
+        print("bench: serving p50 %.2f ms p99 %.2f ms, %.3f J/request" % (
+            serving_rep["latency"]["p50_ms"], serving_rep["latency"]["p99_ms"],
+            serving_rep["energy"].get("j_per_request", float("nan"))), file=sys.stderr, flush=True)
+
     traffic = None
     if os.path.exists(TRAFFIC):
         with open(TRAFFIC) as fh:
@@ -194,6 +207,7 @@ def main():
         "gflops_per_w": (energy or {}).get("time_tuned", {}).get("gflops_per_w"),
         "energy": energy,
         "multichannel": extras,
+        "serving": serving_rep,
         "wall_s_timed": round(t_wall, 4),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),

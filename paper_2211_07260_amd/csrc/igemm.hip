@@ -271,15 +271,30 @@ __global__ __launch_bounds__(256) void igemm_bf16_lds_kernel(IgemmArgs a) {
     const unsigned short *in = static_cast<const unsigned short *>(a.in);
     const unsigned short *wt = static_cast<const unsigned short *>(a.w);
 
-    // stage the halo: chunk k = (pixel p = k / CH, channel chunk q = k % CH)
-    for (int k = threadIdx.x; k < NCHUNK; k += 256) {
-        const int p = k / CH, q = k - p * CH;
-        const int hy = p / HW, hx = p - hy * HW;
-        const int y = y0 - a.ph + hy, x = x0 - a.pw + hx;
-        u32x4 v = u32x4{0u, 0u, 0u, 0u};
-        if (y >= 0 && y < a.h && x >= 0 && x < a.wd)
-            v = *reinterpret_cast<const u32x4 *>(in + (((size_t)b * a.h + y) * a.wd + x) * C + q * 8);
-        *reinterpret_cast<u32x4 *>(lds + p * (C * 2) + 16 * (q ^ lds_swz<C>(hx))) = v;
+    // Stage the halo: chunk k = (pixel p = k / CH, channel chunk q = k % CH).
+    // All of a thread's chunk loads are issued before any LDS store, so the
+    // staging costs about one memory latency; chunks outside the image read a
+    // valid address and are replaced by zeros.
+    {
+        constexpr int ITERS = (NCHUNK + 255) / 256;
+        u32x4 v[ITERS];
+        int off[ITERS];
+#pragma unroll
+        for (int it = 0; it < ITERS; ++it) {
+            const int k = threadIdx.x + it * 256;
+            const int p = k / CH, q = k - p * CH;
+            const int hy = p / HW, hx = p - hy * HW;
+            const int y = y0 - a.ph + hy, x = x0 - a.pw + hx;
+            const bool inside = k < NCHUNK && y >= 0 && y < a.h && x >= 0 && x < a.wd;
+            const size_t src = inside ? (((size_t)b * a.h + y) * a.wd + x) * C + q * 8 : 0;
+            const u32x4 t = *reinterpret_cast<const u32x4 *>(in + src);
+            v[it] = inside ? t : u32x4{0u, 0u, 0u, 0u};
+            off[it] = k < NCHUNK ? p * (C * 2) + 16 * (q ^ lds_swz<C>(hx)) : -1;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int it = 0; it < ITERS; ++it)
+            if (off[it] >= 0) *reinterpret_cast<u32x4 *>(lds + off[it]) = v[it];
     }
     __syncthreads();
 
@@ -289,31 +304,46 @@ __global__ __launch_bounds__(256) void igemm_bf16_lds_kernel(IgemmArgs a) {
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // One filter row: its S * KC steps are unrolled with weight fragments
+    // loaded two steps ahead (they come from L2) and activation fragments one
+    // step ahead (from LDS).
     auto filter_row = [&](int r) {
+        constexpr int NS = S * KC;
         const unsigned char *row = lds + (wave + r) * HW * (C * 2);
+        u32x4 Bq[NS][NT], Aq[NS][kMT];
+        auto ld_b = [&](int k) {
+            const int s = k / KC, kc = k - s * KC;
 #pragma unroll
-        for (int s = 0; s < S; ++s)
-#pragma unroll
-            for (int kc = 0; kc < KC; ++kc) {
-                const int q = kc * 4 + lg;
-                u32x4 B[NT], A[kMT];
-#pragma unroll
-                for (int j = 0; j < NT; ++j) {
-                    const int co = n_blk + j * 16 + li;
-                    B[j] = *reinterpret_cast<const u32x4 *>(wt + (((size_t)co * R + r) * S + s) * C + q * 8);
-                }
-#pragma unroll
-                for (int m = 0; m < kMT; ++m) {
-                    const int hx = m * 16 + li + s;
-                    A[m] = *reinterpret_cast<const u32x4 *>(row + hx * (C * 2) + 16 * (q ^ lds_swz<C>(hx)));
-                }
-#pragma unroll
-                for (int m = 0; m < kMT; ++m)
-#pragma unroll
-                    for (int j = 0; j < NT; ++j)
-                        acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                            __builtin_bit_cast(bf16x8, A[m]), __builtin_bit_cast(bf16x8, B[j]), acc[m][j], 0, 0, 0);
+            for (int j = 0; j < NT; ++j) {
+                const int co = n_blk + j * 16 + li;
+                Bq[k][j] = *reinterpret_cast<const u32x4 *>(wt + (((size_t)co * R + r) * S + s) * C + kc * 32 + lg * 8);
             }
+        };
+        auto ld_a = [&](int k) {
+            const int s = k / KC, kc = k - s * KC;
+            const int q = kc * 4 + lg;
+#pragma unroll
+            for (int m = 0; m < kMT; ++m) {
+                const int hx = m * 16 + li + s;
+                Aq[k][m] = *reinterpret_cast<const u32x4 *>(row + hx * (C * 2) + 16 * (q ^ lds_swz<C>(hx)));
+            }
+        };
+        ld_b(0);
+        if (NS > 1) ld_b(1);
+        ld_a(0);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            if (k + 2 < NS) ld_b(k + 2);
+            if (k + 1 < NS) ld_a(k + 1);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int m = 0; m < kMT; ++m)
+#pragma unroll
+                for (int j = 0; j < NT; ++j)
+                    acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, Aq[k][m]), __builtin_bit_cast(bf16x8, Bq[k][j]), acc[m][j], 0,
+                        0, 0);
+        }
     };
     if constexpr (R <= 7) {  // small filters: the whole walk unrolled (no loop-carried accumulator copies)
 #pragma unroll

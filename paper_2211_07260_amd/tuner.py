@@ -303,7 +303,20 @@ def summarize(sweep_rows, remeasure_rows=None, characterisation=None, workload="
             out["energy_counter_vs_median_ratio"] = {"min": min(ratios), "max": max(ratios)}
     if characterisation:
         out["sensor"] = {k: v for k, v in characterisation.items() if k != "trace"}
+    out["search_difficulty"] = search_difficulty(sweep_rows)
     return nan_to_none(out)
+
+
+def search_difficulty(rows, p_values=(1.0, 1.02, 1.05, 1.1, 1.25, 1.5)):
+    """Proportion of PageRank centrality of good local minima (section V.B) for
+    the time and the energy objective over the measured space."""
+    ok = [r for r in rows if "error" not in r and "e_run_j" in r]
+    cfgs = [r["config"] for r in ok]
+    out = {"p": list(p_values)}
+    for name, key in (("time", "t_run_s"), ("energy", "e_run_j")):
+        _, is_min, prop = gt.ffg_centrality(cfgs, [r[key] for r in ok], p_values)
+        out[name] = {"local_minima": int(sum(is_min)), "proportion_of_centrality": prop}
+    return out
 
 
 def _main(argv=None):
