@@ -228,17 +228,18 @@ __global__ __launch_bounds__(256) void igemm_bf16_mfma_any_kernel(IgemmArgs a, i
         }
 }
 
-// LDS-staged variant.  A workgroup owns a 4-row x 64-column output tile
+// LDS-staged variant.  A workgroup owns a TH-row x 64-column output tile
 // (one row per wave, four 16-pixel M-tiles per wave) for 16*NT output
-// channels.  Its input halo, (4+R-1) x (64+S-1) pixels x C channels, is
+// channels.  Its input halo, (TH+R-1) x (64+S-1) pixels x C channels, is
 // staged in LDS once (zero where the filter overhangs the image), so each
 // input byte crosses L2 once per workgroup instead of once per filter tap.
 // LDS holds pixel-major 16-byte channel chunks; chunk q of halo column hx is
 // stored at slot q ^ swz(hx), which spreads the 16 lanes of an A-fragment read
 // (16 consecutive pixels, same chunk) over distinct banks.  Weights (B) are
+// staged in LDS too when they fit (same swizzle over output channels), else
 // read from L2 as 16-byte fragments; the (s, c-block) walk of one filter row
-// is fully unrolled so the compiler can hoist those loads.
-constexpr int kLdsTH = 4, kLdsTW = 64;
+// is unrolled with fragments loaded ahead of their MFMAs.
+constexpr int kLdsTW = 64;
 
 template <int C>
 __device__ __forceinline__ int lds_swz(int hx) {
@@ -248,25 +249,39 @@ __device__ __forceinline__ int lds_swz(int hx) {
         return (hx >> 2) & 3;
 }
 
-template <int C>
-constexpr int lds_bytes_for(int R, int S) {
-    return (kLdsTH + R - 1) * (kLdsTW + S - 1) * C * 2;
-}
+// Workgroup shape and LDS use of the staged kernel for (C, NT, F): eight
+// output rows with the weights in LDS when halo and weights fit in 160 KiB,
+// else four rows, with the weights in LDS only if they still fit.
+template <int C, int NT, int F>
+struct LdsPlan {
+    static constexpr int kLimit = 163840;
+    static constexpr int halo(int th) { return (th + F - 1) * (kLdsTW + F - 1) * C * 2; }
+    static constexpr int wbytes = 16 * NT * F * F * C * 2;
+    static constexpr int TH = (halo(8) + wbytes <= kLimit) ? 8 : 4;
+    static constexpr bool WL = halo(TH) + wbytes <= kLimit;
+    static constexpr int bytes = halo(TH) + (WL ? wbytes : 0);
+};
 
-template <int C, int NT, int R, int S>
-__global__ __launch_bounds__(256) void igemm_bf16_lds_kernel(IgemmArgs a) {
+// TH output rows (= waves) per workgroup; WL: the workgroup's weights are
+// staged in LDS as well (when halo + weights fit), else read from L2.
+template <int C, int NT, int R, int S, int TH, bool WL>
+__global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a) {
     constexpr int CH = C / 8, KC = C / 32;
-    constexpr int HW = kLdsTW + S - 1, HH = kLdsTH + R - 1;
+    constexpr int HW = kLdsTW + S - 1, HH = TH + R - 1;
     constexpr int NCHUNK = HH * HW * CH;
+    constexpr int NTHR = TH * 64;
+    constexpr int HALO_BYTES = HH * HW * C * 2;
+    constexpr int WCHUNK = 16 * NT * R * S * CH;  // this workgroup's weight chunks
     extern __shared__ __align__(16) unsigned char lds[];
+    unsigned char *wlds = lds + HALO_BYTES;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
-    const int tiles_x = (a.out_w + kLdsTW - 1) / kLdsTW, tiles_y = (a.out_h + kLdsTH - 1) / kLdsTH;
+    const int tiles_x = (a.out_w + kLdsTW - 1) / kLdsTW, tiles_y = (a.out_h + TH - 1) / TH;
     int t = blockIdx.x;
     const int txi = t % tiles_x;
     t /= tiles_x;
     const int tyi = t % tiles_y, b = t / tiles_y;
-    const int x0 = txi * kLdsTW, y0 = tyi * kLdsTH;
+    const int x0 = txi * kLdsTW, y0 = tyi * TH;
     const int n_blk = blockIdx.y * (16 * NT);
     const unsigned short *in = static_cast<const unsigned short *>(a.in);
     const unsigned short *wt = static_cast<const unsigned short *>(a.w);
@@ -276,12 +291,12 @@ __global__ __launch_bounds__(256) void igemm_bf16_lds_kernel(IgemmArgs a) {
     // staging costs about one memory latency; chunks outside the image read a
     // valid address and are replaced by zeros.
     {
-        constexpr int ITERS = (NCHUNK + 255) / 256;
+        constexpr int ITERS = (NCHUNK + NTHR - 1) / NTHR;
         u32x4 v[ITERS];
         int off[ITERS];
 #pragma unroll
         for (int it = 0; it < ITERS; ++it) {
-            const int k = threadIdx.x + it * 256;
+            const int k = threadIdx.x + it * NTHR;
             const int p = k / CH, q = k - p * CH;
             const int hy = p / HW, hx = p - hy * HW;
             const int y = y0 - a.ph + hy, x = x0 - a.pw + hx;
@@ -295,6 +310,28 @@ __global__ __launch_bounds__(256) void igemm_bf16_lds_kernel(IgemmArgs a) {
 #pragma unroll
         for (int it = 0; it < ITERS; ++it)
             if (off[it] >= 0) *reinterpret_cast<u32x4 *>(lds + off[it]) = v[it];
+    }
+    if constexpr (WL) {
+        // weights of output channels n_blk .. n_blk + 16*NT: chunk k = (channel
+        // cl, tap rs, chunk q); chunk q of channel cl at slot q ^ swz(cl), so a
+        // B-fragment read (16 consecutive channels, same chunk) is bank-free
+        constexpr int ITERS = (WCHUNK + NTHR - 1) / NTHR;
+        u32x4 v[ITERS];
+        int off[ITERS];
+#pragma unroll
+        for (int it = 0; it < ITERS; ++it) {
+            const int k = threadIdx.x + it * NTHR;
+            const int cl = k / (R * S * CH), rem = k - cl * (R * S * CH);
+            const int rs = rem / CH, q = rem - rs * CH;
+            const bool ok = k < WCHUNK;
+            v[it] = *reinterpret_cast<const u32x4 *>(
+                wt + (ok ? (((size_t)(n_blk + cl) * R * S + rs) * C + q * 8) : 0));
+            off[it] = ok ? (cl * R * S + rs) * (C * 2) + 16 * (q ^ lds_swz<C>(cl)) : -1;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int it = 0; it < ITERS; ++it)
+            if (off[it] >= 0) *reinterpret_cast<u32x4 *>(wlds + off[it]) = v[it];
     }
     __syncthreads();
 
@@ -315,8 +352,15 @@ __global__ __launch_bounds__(256) void igemm_bf16_lds_kernel(IgemmArgs a) {
             const int s = k / KC, kc = k - s * KC;
 #pragma unroll
             for (int j = 0; j < NT; ++j) {
-                const int co = n_blk + j * 16 + li;
-                Bq[k][j] = *reinterpret_cast<const u32x4 *>(wt + (((size_t)co * R + r) * S + s) * C + kc * 32 + lg * 8);
+                const int cl = j * 16 + li;
+                if constexpr (WL) {
+                    const int q = kc * 4 + lg;
+                    Bq[k][j] = *reinterpret_cast<const u32x4 *>(wlds + (cl * R * S + r * S + s) * (C * 2) +
+                                                                16 * (q ^ lds_swz<C>(cl)));
+                } else {
+                    Bq[k][j] = *reinterpret_cast<const u32x4 *>(
+                        wt + (((size_t)(n_blk + cl) * R + r) * S + s) * C + kc * 32 + lg * 8);
+                }
             }
         };
         auto ld_a = [&](int k) {
@@ -496,9 +540,11 @@ const void *valu_kernel_for(int f, int c) {
 struct LdsEntry {
     int c, nt, f;
     const void *fn;
-    int lds;
+    int lds, th;
 };
-#define GT_L(C, NT, F) {C, NT, F, (const void *)&igemm_bf16_lds_kernel<C, NT, F, F>, lds_bytes_for<C>(F, F)}
+#define GT_L(C, NT, F)                                                                                     \
+    {C, NT, F, (const void *)&igemm_bf16_lds_kernel<C, NT, F, F, LdsPlan<C, NT, F>::TH, LdsPlan<C, NT, F>::WL>, \
+     LdsPlan<C, NT, F>::bytes, LdsPlan<C, NT, F>::TH}
 const LdsEntry kLdsTable[] = {
     GT_L(64, 4, 1), GT_L(64, 4, 3), GT_L(64, 4, 5), GT_L(64, 4, 7), GT_L(64, 4, 9),
     GT_L(64, 2, 1), GT_L(64, 2, 3), GT_L(64, 2, 5), GT_L(64, 2, 7), GT_L(64, 2, 9),
@@ -562,11 +608,11 @@ int launch_igemm(const gt_problem &p, const gt_conv_config &, const void *in, co
     void *args[] = {&a};
     if (p.kind == GT_IGEMM_BF16_MFMA && p.filt_h == p.filt_w) {
         if (const LdsEntry *e = lds_kernel_for(p.filt_h, p.c_in, p.c_out)) {
-            const int64_t tiles = (int64_t)p.n * ((p.out_h + kLdsTH - 1) / kLdsTH) * ((p.out_w + kLdsTW - 1) / kLdsTW);
+            const int64_t tiles = (int64_t)p.n * ((p.out_h + e->th - 1) / e->th) * ((p.out_w + kLdsTW - 1) / kLdsTW);
             if (e->lds > 65536)
                 GT_HIP_CHECK(hipFuncSetAttribute(e->fn, hipFuncAttributeMaxDynamicSharedMemorySize, e->lds));
             dim3 grid((unsigned)tiles, (unsigned)(p.c_out / (16 * e->nt)));
-            GT_HIP_CHECK(hipLaunchKernel(e->fn, grid, dim3(256), args, (size_t)e->lds, s));
+            GT_HIP_CHECK(hipLaunchKernel(e->fn, grid, dim3(64 * e->th), args, (size_t)e->lds, s));
             return GT_OK;
         }
     }
