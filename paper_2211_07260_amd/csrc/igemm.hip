@@ -249,29 +249,39 @@ __device__ __forceinline__ int lds_swz(int hx) {
         return (hx >> 2) & 3;
 }
 
-// Workgroup shape and LDS use of the staged kernel for (C, NT, F): eight
-// output rows with the weights in LDS when halo and weights fit in 160 KiB,
-// else four rows, with the weights in LDS only if they still fit.
+// Where the workgroup's weights live.
+enum WeightMode { kWeightsL2 = 0, kWeightsLds = 1, kWeightsLdsByRow = 2 };
+
+// Workgroup shape and LDS use of the staged kernel for (C, NT, F), within
+// 160 KiB: eight output rows with all weights in LDS if that fits; else four
+// rows with all weights, or with one filter row of weights double-buffered
+// (the next row's weights load while the current row computes); else four
+// rows with the weights read from L2.
 template <int C, int NT, int F>
 struct LdsPlan {
     static constexpr int kLimit = 163840;
     static constexpr int halo(int th) { return (th + F - 1) * (kLdsTW + F - 1) * C * 2; }
     static constexpr int wbytes = 16 * NT * F * F * C * 2;
+    static constexpr int wrow = 16 * NT * F * C * 2;
     static constexpr int TH = (halo(8) + wbytes <= kLimit) ? 8 : 4;
-    static constexpr bool WL = halo(TH) + wbytes <= kLimit;
-    static constexpr int bytes = halo(TH) + (WL ? wbytes : 0);
+    static constexpr int WM = halo(TH) + wbytes <= kLimit       ? kWeightsLds
+                              : halo(TH) + 2 * wrow <= kLimit ? kWeightsLdsByRow
+                                                              : kWeightsL2;
+    static constexpr int bytes = halo(TH) + (WM == kWeightsLds ? wbytes : WM == kWeightsLdsByRow ? 2 * wrow : 0);
 };
 
-// TH output rows (= waves) per workgroup; WL: the workgroup's weights are
-// staged in LDS as well (when halo + weights fit), else read from L2.
-template <int C, int NT, int R, int S, int TH, bool WL>
+// TH output rows (= waves) per workgroup; WM: weight placement (WeightMode).
+template <int C, int NT, int R, int S, int TH, int WM>
 __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a) {
+    constexpr bool WL = WM == kWeightsLds, WROW = WM == kWeightsLdsByRow;
     constexpr int CH = C / 8, KC = C / 32;
     constexpr int HW = kLdsTW + S - 1, HH = TH + R - 1;
     constexpr int NCHUNK = HH * HW * CH;
     constexpr int NTHR = TH * 64;
     constexpr int HALO_BYTES = HH * HW * C * 2;
-    constexpr int WCHUNK = 16 * NT * R * S * CH;  // this workgroup's weight chunks
+    constexpr int WCHUNK = 16 * NT * R * S * CH;     // this workgroup's weight chunks
+    constexpr int RCHUNK = 16 * NT * S * CH;         // ... of one filter row
+    constexpr int WROW_BYTES = 16 * NT * S * C * 2;
     extern __shared__ __align__(16) unsigned char lds[];
     unsigned char *wlds = lds + HALO_BYTES;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -333,6 +343,35 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a) {
         for (int it = 0; it < ITERS; ++it)
             if (off[it] >= 0) *reinterpret_cast<u32x4 *>(wlds + off[it]) = v[it];
     }
+    // one filter row of weights (row-buffered mode): chunk k = (channel cl,
+    // tap s, chunk q) of row r, stored at (cl*S + s) with the same swizzle
+    constexpr int RITERS = (RCHUNK + NTHR - 1) / NTHR;
+    auto wrow_load = [&](int r, u32x4 (&v)[RITERS]) {
+#pragma unroll
+        for (int it = 0; it < RITERS; ++it) {
+            const int k = threadIdx.x + it * NTHR;
+            const int cl = k / (S * CH), rem = k - cl * (S * CH);
+            const int sx = rem / CH, q = rem - sx * CH;
+            v[it] = *reinterpret_cast<const u32x4 *>(
+                wt + (k < RCHUNK ? (((size_t)(n_blk + cl) * R + r) * S + sx) * C + q * 8 : 0));
+        }
+    };
+    auto wrow_store = [&](int buf, const u32x4 (&v)[RITERS]) {
+#pragma unroll
+        for (int it = 0; it < RITERS; ++it) {
+            const int k = threadIdx.x + it * NTHR;
+            const int cl = k / (S * CH), rem = k - cl * (S * CH);
+            const int sx = rem / CH, q = rem - sx * CH;
+            if (k < RCHUNK)
+                *reinterpret_cast<u32x4 *>(wlds + buf * WROW_BYTES + (cl * S + sx) * (C * 2) +
+                                           16 * (q ^ lds_swz<C>(cl))) = v[it];
+        }
+    };
+    if constexpr (WROW) {
+        u32x4 v[RITERS];
+        wrow_load(0, v);
+        wrow_store(0, v);
+    }
     __syncthreads();
 
     f32x4 acc[kMT][NT];
@@ -356,6 +395,10 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a) {
                 if constexpr (WL) {
                     const int q = kc * 4 + lg;
                     Bq[k][j] = *reinterpret_cast<const u32x4 *>(wlds + (cl * R * S + r * S + s) * (C * 2) +
+                                                                16 * (q ^ lds_swz<C>(cl)));
+                } else if constexpr (WROW) {
+                    const int q = kc * 4 + lg;
+                    Bq[k][j] = *reinterpret_cast<const u32x4 *>(wlds + (r & 1) * WROW_BYTES + (cl * S + s) * (C * 2) +
                                                                 16 * (q ^ lds_swz<C>(cl)));
                 } else {
                     Bq[k][j] = *reinterpret_cast<const u32x4 *>(
@@ -389,7 +432,18 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a) {
                         0, 0);
         }
     };
-    if constexpr (R <= 7) {  // small filters: the whole walk unrolled (no loop-carried accumulator copies)
+    if constexpr (WROW) {
+        // next row's weights load from L2 while this row computes; the barrier
+        // after the store keeps the two buffers' readers and writer apart
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            u32x4 v[RITERS];
+            if (r + 1 < R) wrow_load(r + 1, v);
+            filter_row(r);
+            if (r + 1 < R) wrow_store((r + 1) & 1, v);
+            __syncthreads();
+        }
+    } else if constexpr (R <= 7) {  // small filters: the whole walk unrolled (no loop-carried accumulator copies)
 #pragma unroll
         for (int r = 0; r < R; ++r) filter_row(r);
     } else {
@@ -543,7 +597,7 @@ struct LdsEntry {
     int lds, th;
 };
 #define GT_L(C, NT, F)                                                                                     \
-    {C, NT, F, (const void *)&igemm_bf16_lds_kernel<C, NT, F, F, LdsPlan<C, NT, F>::TH, LdsPlan<C, NT, F>::WL>, \
+    {C, NT, F, (const void *)&igemm_bf16_lds_kernel<C, NT, F, F, LdsPlan<C, NT, F>::TH, LdsPlan<C, NT, F>::WM>, \
      LdsPlan<C, NT, F>::bytes, LdsPlan<C, NT, F>::TH}
 const LdsEntry kLdsTable[] = {
     GT_L(64, 4, 1), GT_L(64, 4, 3), GT_L(64, 4, 5), GT_L(64, 4, 7), GT_L(64, 4, 9),
