@@ -52,9 +52,10 @@ def cpu_baseline(img, w, min_seconds=8.0):
             "sample": "full 4096x4096x17x17 FP64 cross-correlation x%d (%.1f s wall)" % (reps, el)}
 
 
-def igemm_extras(gt, torch, dev, steps=20):
+def igemm_extras(gt, torch, dev, steps=20, energy=True):
     """Multi-channel conv (N=16, C_in=C_out=64, 128x128, same padding), BF16
-    MFMA and FP32 VALU paths on the same BF16-valued data: ms and TFLOP/s."""
+    MFMA and FP32 VALU paths on the same BF16-valued data: ms, TFLOP/s and
+    (measured with measure_time_energy) GFLOP/s/W."""
     from synthetic import conv_inputs
     res = {}
     for f in (3, 5):
@@ -73,7 +74,14 @@ def igemm_extras(gt, torch, dev, steps=20):
             e1.record()
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / steps
-            res["%s_f%d" % (name, f)] = {"ms": round(ms, 5), "tflops": round(gt.problem_flops(p) / ms / 1e9, 2)}
+            r = {"ms": round(ms, 5), "tflops": round(gt.problem_flops(p) / ms / 1e9, 2)}
+            if energy:
+                try:
+                    m = gt.measure_time_energy(p, (64, 1, 1, 1, 0, 0), dx, dw, out, window_s=1.0, discard_s=0.3)
+                    r.update(gflops_per_w=round(m["gflops_per_w"], 3), p_median_w=m["p_median_w"])
+                except gt.GreentuneError as e:
+                    r["energy_error"] = str(e)
+            res["%s_f%d" % (name, f)] = r
     return res
 
 
@@ -167,7 +175,7 @@ def main():
 
     extras = None
     if not args.no_extras:
-        extras = igemm_extras(gt, torch, dev)
+        extras = igemm_extras(gt, torch, dev, energy=not args.no_energy)
 
     serving_rep = None
     if not args.no_serving:

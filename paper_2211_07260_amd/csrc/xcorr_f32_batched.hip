@@ -34,7 +34,18 @@ __global__ __launch_bounds__(1024) void xcorr_f32_batched_kernel(const BatchDesc
     extern __shared__ __align__(16) float lds[];
     typedef const __attribute__((address_space(4))) BatchDesc cdesc;
     cdesc *d = (cdesc *)desc;
-    for (int64_t item = blockIdx.x; item < total_tiles; item += gridDim.x) {
+    // Workgroups are dispatched round-robin over the 8 XCDs.  When the grid is
+    // a multiple of 8, XCD x walks the x-th eighth of the tile list, so
+    // neighbouring tiles of one convolution share that XCD's L2.
+    int64_t first = blockIdx.x, last = total_tiles, step = gridDim.x;
+    if ((gridDim.x & 7) == 0) {
+        const int64_t chunk = (total_tiles + 7) / 8;
+        const int x = blockIdx.x & 7;
+        first = x * chunk + (blockIdx.x >> 3);
+        last = min(total_tiles, (int64_t)(x + 1) * chunk);
+        step = gridDim.x >> 3;
+    }
+    for (int64_t item = first; item < last; item += step) {
         // the convolution holding this tile: last descriptor with tile_begin <= item
         int lo = 0, hi = n_desc - 1;
         while (lo < hi) {
