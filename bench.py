@@ -78,7 +78,8 @@ def igemm_extras(gt, torch, dev, steps=20, energy=True):
             if energy:
                 try:
                     m = gt.measure_time_energy(p, (64, 1, 1, 1, 0, 0), dx, dw, out, window_s=1.0, discard_s=0.3)
-                    r.update(gflops_per_w=round(m["gflops_per_w"], 3), p_median_w=m["p_median_w"])
+                    r.update(gflops_per_w=round(m["gflops_per_w"], 3), p_median_w=m["p_median_w"],
+                             sclk_mhz=round(m["sclk_act_mhz"], 1))
                 except gt.GreentuneError as e:
                     r["energy_error"] = str(e)
             res["%s_f%d" % (name, f)] = r

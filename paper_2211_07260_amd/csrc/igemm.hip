@@ -22,6 +22,9 @@
 //   v_fmac acc, s_x, v_w with the weights in VGPRs (read through L1/L2).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
+
 #include "gt_internal.hpp"
 
 namespace gt {
@@ -229,25 +232,29 @@ __global__ __launch_bounds__(256) void igemm_bf16_mfma_any_kernel(IgemmArgs a, i
 }
 
 // LDS-staged variant.  A workgroup owns a TH-row x 64-column output tile
-// (one row per wave, four 16-pixel M-tiles per wave) for 16*NT output
-// channels.  Its input halo, (TH+R-1) x (64+S-1) pixels x C channels, is
-// staged in LDS once (zero where the filter overhangs the image), so each
-// input byte crosses L2 once per workgroup instead of once per filter tap.
-// LDS holds pixel-major 16-byte channel chunks; chunk q of halo column hx is
-// stored at slot q ^ swz(hx), which spreads the 16 lanes of an A-fragment read
-// (16 consecutive pixels, same chunk) over distinct banks.  Weights (B) are
-// staged in LDS too when they fit (same swizzle over output channels), else
-// read from L2 as 16-byte fragments; the (s, c-block) walk of one filter row
-// is unrolled with fragments loaded ahead of their MFMAs.
+// (one row per wave) for 16*NT output channels.  Its input halo,
+// (TH+R-1) x (64+S-1) pixels x C channels, sits in LDS (zero where the filter
+// overhangs the image), so each input byte crosses L2 about once per strip
+// instead of once per filter tap, and the weights sit in LDS too when they
+// fit.
+//
+// A wave's 64 pixels form kMT = 4 M-tiles, interleaved: row i of M-tile m is
+// pixel 4*i + m.  For filter tap s, M-tile m then needs pixels 4*i + m + s,
+// which is the fragment F(m + s) with lane i holding pixel 4*i + t; so one
+// filter row and 32-channel block reads kMT + S - 1 activation fragments from
+// LDS instead of kMT * S.
+//
+// LDS layout.  Every 32-channel block is a plane of 64-byte pixel records,
+// and chunk c (8 channels) of a record at position pos sits at 16-byte slot
+// c ^ ((pos >> 2) & 3); 16 consecutive positions then cover all 64 banks once,
+// and every fragment read below is 16 consecutive positions of one chunk.
+// Halo rows store pixel hx at position (hx & 3) * HW4 + (hx >> 2), so F(t)
+// is 16 consecutive positions.  Weights are stored [r][s][c-block][channel],
+// so a B fragment (16 consecutive output channels) is 16 consecutive records.
 constexpr int kLdsTW = 64;
+constexpr int kRec = 64;  // bytes of one record: 32 BF16 channels
 
-template <int C>
-__device__ __forceinline__ int lds_swz(int hx) {
-    if constexpr (C == 64)
-        return (hx >> 1) & 7;
-    else
-        return (hx >> 2) & 3;
-}
+__device__ __forceinline__ int rec_slot(int c, int pos) { return c ^ ((pos >> 2) & 3); }
 
 // Where the workgroup's weights live.
 enum WeightMode { kWeightsL2 = 0, kWeightsLds = 1, kWeightsLdsByRow = 2 };
@@ -260,7 +267,8 @@ enum WeightMode { kWeightsL2 = 0, kWeightsLds = 1, kWeightsLdsByRow = 2 };
 template <int C, int NT, int F>
 struct LdsPlan {
     static constexpr int kLimit = 163840;
-    static constexpr int halo(int th) { return (th + F - 1) * (kLdsTW + F - 1) * C * 2; }
+    static constexpr int HW4 = (kLdsTW + F - 1 + 3) / 4;
+    static constexpr int halo(int th) { return (th + F - 1) * 4 * HW4 * C * 2; }
     static constexpr int wbytes = 16 * NT * F * F * C * 2;
     static constexpr int wrow = 16 * NT * F * C * 2;
     static constexpr int TH = (halo(8) + wbytes <= kLimit) ? 8 : 4;
@@ -270,83 +278,106 @@ struct LdsPlan {
     static constexpr int bytes = halo(TH) + (WM == kWeightsLds ? wbytes : WM == kWeightsLdsByRow ? 2 * wrow : 0);
 };
 
-// TH output rows (= waves) per workgroup; WM: weight placement (WeightMode).
-template <int C, int NT, int R, int S, int TH, int WM>
-__global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a) {
-    constexpr bool WL = WM == kWeightsLds, WROW = WM == kWeightsLdsByRow;
-    constexpr int CH = C / 8, KC = C / 32;
-    constexpr int HW = kLdsTW + S - 1, HH = TH + R - 1;
-    constexpr int NCHUNK = HH * HW * CH;
-    constexpr int NTHR = TH * 64;
-    constexpr int HALO_BYTES = HH * HW * C * 2;
-    constexpr int WCHUNK = 16 * NT * R * S * CH;     // this workgroup's weight chunks
-    constexpr int RCHUNK = 16 * NT * S * CH;         // ... of one filter row
-    constexpr int WROW_BYTES = 16 * NT * S * C * 2;
-    extern __shared__ __align__(16) unsigned char lds[];
-    unsigned char *wlds = lds + HALO_BYTES;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int li = lane & 15, lg = lane >> 4;
-    const int tiles_x = (a.out_w + kLdsTW - 1) / kLdsTW, tiles_y = (a.out_h + TH - 1) / TH;
-    int t = blockIdx.x;
-    const int txi = t % tiles_x;
-    t /= tiles_x;
-    const int tyi = t % tiles_y, b = t / tiles_y;
-    const int x0 = txi * kLdsTW, y0 = tyi * TH;
-    const int n_blk = blockIdx.y * (16 * NT);
-    const unsigned short *in = static_cast<const unsigned short *>(a.in);
-    const unsigned short *wt = static_cast<const unsigned short *>(a.w);
-
-    // Stage the halo: chunk k = (pixel p = k / CH, channel chunk q = k % CH).
-    // All of a thread's chunk loads are issued before any LDS store, so the
-    // staging costs about one memory latency; chunks outside the image read a
-    // valid address and are replaced by zeros.
-    {
-        constexpr int ITERS = (NCHUNK + NTHR - 1) / NTHR;
-        u32x4 v[ITERS];
-        int off[ITERS];
+// Rows hy0 .. hy0+ROWS-1 of a tile's input halo: chunk k = (pixel p = k / CH,
+// channel chunk q = k % CH).  LDS holds the halo as a ring of HH pixel rows:
+// halo row hy of the tile whose first output row is y0 lives in ring slot
+// (y0 + hy) % HH, so the next tile down the same strip finds its first R-1
+// rows in place.
+template <int C, int HW, int HH, int NTHR, int ROWS>
+struct HaloRows {
+    static constexpr int CH = C / 8, KC = C / 32, HW4 = (HW + 3) / 4;
+    static constexpr int ROWB = 4 * HW4 * kRec, PLANE = HH * ROWB;
+    static constexpr int NCHUNK = ROWS * HW * CH, ITERS = (NCHUNK + NTHR - 1) / NTHR;
+    // every load of a thread is issued before any is used; chunks outside the
+    // image read a valid address and are replaced by zeros
+    __device__ static void load(const IgemmArgs &a, int b, int y0, int x0, int hy0, u32x4 (&v)[ITERS]) {
+        const unsigned short *in = static_cast<const unsigned short *>(a.in);
 #pragma unroll
         for (int it = 0; it < ITERS; ++it) {
             const int k = threadIdx.x + it * NTHR;
             const int p = k / CH, q = k - p * CH;
-            const int hy = p / HW, hx = p - hy * HW;
+            const int hy = hy0 + p / HW, hx = p % HW;
             const int y = y0 - a.ph + hy, x = x0 - a.pw + hx;
             const bool inside = k < NCHUNK && y >= 0 && y < a.h && x >= 0 && x < a.wd;
             const size_t src = inside ? (((size_t)b * a.h + y) * a.wd + x) * C + q * 8 : 0;
             const u32x4 t = *reinterpret_cast<const u32x4 *>(in + src);
             v[it] = inside ? t : u32x4{0u, 0u, 0u, 0u};
-            off[it] = k < NCHUNK ? p * (C * 2) + 16 * (q ^ lds_swz<C>(hx)) : -1;
         }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int it = 0; it < ITERS; ++it)
-            if (off[it] >= 0) *reinterpret_cast<u32x4 *>(lds + off[it]) = v[it];
     }
-    if constexpr (WL) {
-        // weights of output channels n_blk .. n_blk + 16*NT: chunk k = (channel
-        // cl, tap rs, chunk q); chunk q of channel cl at slot q ^ swz(cl), so a
-        // B-fragment read (16 consecutive channels, same chunk) is bank-free
-        constexpr int ITERS = (WCHUNK + NTHR - 1) / NTHR;
-        u32x4 v[ITERS];
-        int off[ITERS];
+    __device__ static void store(unsigned char *halo, int y0, int hy0, const u32x4 (&v)[ITERS]) {
 #pragma unroll
         for (int it = 0; it < ITERS; ++it) {
             const int k = threadIdx.x + it * NTHR;
-            const int cl = k / (R * S * CH), rem = k - cl * (R * S * CH);
-            const int rs = rem / CH, q = rem - rs * CH;
-            const bool ok = k < WCHUNK;
-            v[it] = *reinterpret_cast<const u32x4 *>(
-                wt + (ok ? (((size_t)(n_blk + cl) * R * S + rs) * C + q * 8) : 0));
-            off[it] = ok ? (cl * R * S + rs) * (C * 2) + 16 * (q ^ lds_swz<C>(cl)) : -1;
+            const int p = k / CH, q = k - p * CH;
+            const int slot = (y0 + hy0 + p / HW) % HH, hx = p % HW;
+            const int pos = (hx & 3) * HW4 + (hx >> 2);
+            if (k < NCHUNK)
+                *reinterpret_cast<u32x4 *>(halo + (q >> 2) * PLANE + slot * ROWB + pos * kRec +
+                                           16 * rec_slot(q & 3, pos)) = v[it];
         }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int it = 0; it < ITERS; ++it)
-            if (off[it] >= 0) *reinterpret_cast<u32x4 *>(wlds + off[it]) = v[it];
     }
+};
+
+// Persistent: the grid holds about as many workgroups as are resident at
+// once, and workgroup g runs tiles_per_wg consecutive tiles, ordered down a
+// 64-column strip of one image.  A tile's successor in the strip needs only
+// TH new halo rows (the ring keeps the other R-1); they are loaded into
+// registers while the tile computes and written to LDS once every wave is
+// done with the rows they replace.
+// TH output rows (= waves) per workgroup; WM: weight placement (WeightMode).
+template <int C, int NT, int R, int S, int TH, int WM>
+__global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, int tiles_per_wg) {
+    constexpr bool WL = WM == kWeightsLds, WROW = WM == kWeightsLdsByRow;
+    constexpr int CH = C / 8, KC = C / 32;
+    constexpr int HW = kLdsTW + S - 1, HH = TH + R - 1;
+    constexpr int NTHR = TH * 64;
+    typedef HaloRows<C, HW, HH, NTHR, HH> Full;
+    typedef HaloRows<C, HW, HH, NTHR, TH> Next;
+    constexpr int HW4 = Full::HW4, ROWB = Full::ROWB, PLANE = Full::PLANE;
+    constexpr int TAPB = 16 * NT * kRec;  // one (tap, c-block) of the workgroup's weights
+    constexpr int WROW_BYTES = S * KC * TAPB;
+    constexpr int WCHUNK = 16 * NT * R * S * CH;  // this workgroup's weight chunks
+    constexpr int RCHUNK = 16 * NT * S * CH;      // ... of one filter row
+    // weight loads from L2 would wait behind the prefetch (loads complete in
+    // order), so that mode loads the next rows after the tile instead
+    constexpr bool PREFETCH = WM != kWeightsL2;
+    constexpr int BD = WM == kWeightsL2 ? 2 : 1;  // weight fragments are loaded BD steps ahead
+    // weights first (offset 0), then the halo planes
+    extern __shared__ __align__(16) unsigned char lds[];
+    unsigned char *wlds = lds;
+    unsigned char *halo = lds + (WL ? R * S * KC * TAPB : WROW ? 2 * WROW_BYTES : 0);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int tiles_x = (a.out_w + kLdsTW - 1) / kLdsTW, tiles_y = (a.out_h + TH - 1) / TH;
+    const int n_tiles = a.n * tiles_x * tiles_y;
+    // Workgroups are dispatched round-robin over the 8 XCDs; when the grid is
+    // a multiple of 8, XCD x gets the x-th eighth of the workgroup indices, so
+    // neighbouring runs of tiles share an L2.
+    int g = blockIdx.x;
+    if ((gridDim.x & 7) == 0) g = (g & 7) * (gridDim.x >> 3) + (g >> 3);
+    const int t_begin = g * tiles_per_wg;
+    const int t_end = min(n_tiles, t_begin + tiles_per_wg);
+    if (t_begin >= t_end) return;  // uniform over the workgroup
+    const int n_blk = blockIdx.y * (16 * NT);
+    const unsigned short *wt = static_cast<const unsigned short *>(a.w);
+
+    // tile t -> (image b, column strip, row block), row block fastest
+    auto tile_origin = [&](int t, int &b, int &y0, int &x0) {
+        const int tyi = t % tiles_y;
+        t /= tiles_y;
+        const int txi = t % tiles_x;
+        b = t / tiles_x;
+        y0 = tyi * TH;
+        x0 = txi * kLdsTW;
+    };
+    // weight chunk q of (channel cl, tap) -> LDS offset within a [tap][c-block][channel] block
+    auto wofs = [&](int tap, int cl, int q) {
+        return ((tap * KC + (q >> 2)) * (16 * NT) + cl) * kRec + 16 * rec_slot(q & 3, cl);
+    };
     // one filter row of weights (row-buffered mode): chunk k = (channel cl,
-    // tap s, chunk q) of row r, stored at (cl*S + s) with the same swizzle
+    // tap s, chunk q) of row r
     constexpr int RITERS = (RCHUNK + NTHR - 1) / NTHR;
-    auto wrow_load = [&](int r, u32x4 (&v)[RITERS]) {
+    auto wrow_load = [&](int r, u32x4(&v)[RITERS]) {
 #pragma unroll
         for (int it = 0; it < RITERS; ++it) {
             const int k = threadIdx.x + it * NTHR;
@@ -356,17 +387,45 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a) {
                 wt + (k < RCHUNK ? (((size_t)(n_blk + cl) * R + r) * S + sx) * C + q * 8 : 0));
         }
     };
-    auto wrow_store = [&](int buf, const u32x4 (&v)[RITERS]) {
+    auto wrow_store = [&](int buf, const u32x4(&v)[RITERS]) {
 #pragma unroll
         for (int it = 0; it < RITERS; ++it) {
             const int k = threadIdx.x + it * NTHR;
             const int cl = k / (S * CH), rem = k - cl * (S * CH);
             const int sx = rem / CH, q = rem - sx * CH;
-            if (k < RCHUNK)
-                *reinterpret_cast<u32x4 *>(wlds + buf * WROW_BYTES + (cl * S + sx) * (C * 2) +
-                                           16 * (q ^ lds_swz<C>(cl))) = v[it];
+            if (k < RCHUNK) *reinterpret_cast<u32x4 *>(wlds + buf * WROW_BYTES + wofs(sx, cl, q)) = v[it];
         }
     };
+
+    {
+        int b, y0, x0;
+        tile_origin(t_begin, b, y0, x0);
+        u32x4 v[Full::ITERS];
+        Full::load(a, b, y0, x0, 0, v);
+        Full::store(halo, y0, 0, v);
+    }
+    if constexpr (WL) {
+        // all weights of output channels n_blk .. n_blk + 16*NT, staged once:
+        // chunk k = (channel cl, tap rs, chunk q)
+        constexpr int ITERS = (WCHUNK + NTHR - 1) / NTHR;
+        u32x4 v[ITERS];
+#pragma unroll
+        for (int it = 0; it < ITERS; ++it) {
+            const int k = threadIdx.x + it * NTHR;
+            const int cl = k / (R * S * CH), rem = k - cl * (R * S * CH);
+            const int rs = rem / CH, q = rem - rs * CH;
+            v[it] = *reinterpret_cast<const u32x4 *>(
+                wt + (k < WCHUNK ? (((size_t)(n_blk + cl) * R * S + rs) * C + q * 8) : 0));
+        }
+#pragma unroll
+        for (int it = 0; it < ITERS; ++it) {
+            const int k = threadIdx.x + it * NTHR;
+            const int cl = k / (R * S * CH), rem = k - cl * (R * S * CH);
+            const int rs = rem / CH, q = rem - rs * CH;
+            if (k < WCHUNK) *reinterpret_cast<u32x4 *>(wlds + wofs(rs, cl, q)) = v[it];
+        }
+    }
+    int wb = 0;  // row-buffered mode: the LDS buffer holding the current filter row
     if constexpr (WROW) {
         u32x4 v[RITERS];
         wrow_load(0, v);
@@ -374,97 +433,138 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a) {
     }
     __syncthreads();
 
-    f32x4 acc[kMT][NT];
+    // this lane's byte offsets: F(t) within a halo row (t < kMT + S - 1), and
+    // its B-fragment record within a (tap, c-block) weight block
+    int aofs[kMT + S - 1];
 #pragma unroll
-    for (int m = 0; m < kMT; ++m)
-#pragma unroll
-        for (int j = 0; j < NT; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    // One filter row: its S * KC steps are unrolled with weight fragments
-    // loaded two steps ahead (they come from L2) and activation fragments one
-    // step ahead (from LDS).
-    auto filter_row = [&](int r) {
-        constexpr int NS = S * KC;
-        const unsigned char *row = lds + (wave + r) * HW * (C * 2);
-        u32x4 Bq[NS][NT], Aq[NS][kMT];
-        auto ld_b = [&](int k) {
-            const int s = k / KC, kc = k - s * KC;
-#pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                const int cl = j * 16 + li;
-                if constexpr (WL) {
-                    const int q = kc * 4 + lg;
-                    Bq[k][j] = *reinterpret_cast<const u32x4 *>(wlds + (cl * R * S + r * S + s) * (C * 2) +
-                                                                16 * (q ^ lds_swz<C>(cl)));
-                } else if constexpr (WROW) {
-                    const int q = kc * 4 + lg;
-                    Bq[k][j] = *reinterpret_cast<const u32x4 *>(wlds + (r & 1) * WROW_BYTES + (cl * S + s) * (C * 2) +
-                                                                16 * (q ^ lds_swz<C>(cl)));
-                } else {
-                    Bq[k][j] = *reinterpret_cast<const u32x4 *>(
-                        wt + (((size_t)(n_blk + cl) * R + r) * S + s) * C + kc * 32 + lg * 8);
-                }
-            }
-        };
-        auto ld_a = [&](int k) {
-            const int s = k / KC, kc = k - s * KC;
-            const int q = kc * 4 + lg;
-#pragma unroll
-            for (int m = 0; m < kMT; ++m) {
-                const int hx = m * 16 + li + s;
-                Aq[k][m] = *reinterpret_cast<const u32x4 *>(row + hx * (C * 2) + 16 * (q ^ lds_swz<C>(hx)));
-            }
-        };
-        ld_b(0);
-        if (NS > 1) ld_b(1);
-        ld_a(0);
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            if (k + 2 < NS) ld_b(k + 2);
-            if (k + 1 < NS) ld_a(k + 1);
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int m = 0; m < kMT; ++m)
-#pragma unroll
-                for (int j = 0; j < NT; ++j)
-                    acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        __builtin_bit_cast(bf16x8, Aq[k][m]), __builtin_bit_cast(bf16x8, Bq[k][j]), acc[m][j], 0,
-                        0, 0);
-        }
-    };
-    if constexpr (WROW) {
-        // next row's weights load from L2 while this row computes; the barrier
-        // after the store keeps the two buffers' readers and writer apart
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            u32x4 v[RITERS];
-            if (r + 1 < R) wrow_load(r + 1, v);
-            filter_row(r);
-            if (r + 1 < R) wrow_store((r + 1) & 1, v);
-            __syncthreads();
-        }
-    } else if constexpr (R <= 7) {  // small filters: the whole walk unrolled (no loop-carried accumulator copies)
-#pragma unroll
-        for (int r = 0; r < R; ++r) filter_row(r);
-    } else {
-#pragma unroll 1
-        for (int r = 0; r < R; ++r) filter_row(r);
+    for (int t = 0; t < kMT + S - 1; ++t) {
+        const int pos = (t & 3) * HW4 + (t >> 2) + li;
+        aofs[t] = pos * kRec + 16 * rec_slot(lg, pos);
     }
+    const int bofs = li * kRec + 16 * rec_slot(lg, li);
 
-    // D[m = 4*lg + e][n = li] of M-tile m: pixel (y0 + wave, x0 + 16*m + 4*lg + e)
-    const int y = y0 + wave;
-    if (y < a.out_h) {
+    for (int t = t_begin; t < t_end; ++t) {
+        const bool more = t + 1 < t_end;                   // uniform over the workgroup
+        const bool down = more && (t + 1) % tiles_y != 0;  // the next tile is the one below
+        int b, y0, x0;
+        tile_origin(t, b, y0, x0);
+        // the next tile's TH new rows: its halo rows R-1 .. R+TH-2
+        u32x4 nh[Next::ITERS];
+        if constexpr (PREFETCH)
+            if (down) Next::load(a, b, y0 + TH, x0, R - 1, nh);
+        // opaque per tile, so weight loads from L2 are not hoisted out of the tile loop
+        const unsigned short *wtt = wt;
+        asm volatile("" : "+s"(wtt));
+
+        f32x4 acc[kMT][NT];
 #pragma unroll
         for (int m = 0; m < kMT; ++m)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int x = x0 + m * 16 + lg * 4 + e;
-                if (x < a.out_w) {
-                    float *dst = a.out + (((size_t)b * a.out_h + y) * a.out_w + x) * a.c_out + n_blk + li;
+            for (int j = 0; j < NT; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+        // One filter row: steps k = (c-block kc, tap s), s fastest.  Step k
+        // uses F(s) .. F(s+kMT-1) of block kc and the weights of (r, s, kc);
+        // the activation fragments a step newly needs are loaded one step
+        // ahead, the weight fragments BD steps ahead.
+        auto filter_row = [&](int r) {
+            constexpr int NS = KC * S;
+            const unsigned char *arow = halo + ((y0 + wave + r) % HH) * ROWB;
+            u32x4 Af[KC][kMT + S - 1], Bq[NS][NT];
+            auto ld_b = [&](int k) {
+                const int kc = k / S, s = k - kc * S;
 #pragma unroll
-                    for (int j = 0; j < NT; ++j) dst[j * 16] = acc[m][j][e];
+                for (int j = 0; j < NT; ++j) {
+                    if constexpr (WL) {
+                        Bq[k][j] = *reinterpret_cast<const u32x4 *>(wlds + ((r * S + s) * KC + kc) * TAPB + j * 16 * kRec + bofs);
+                    } else if constexpr (WROW) {
+                        Bq[k][j] = *reinterpret_cast<const u32x4 *>(wlds + wb * WROW_BYTES + (s * KC + kc) * TAPB + j * 16 * kRec + bofs);
+                    } else {
+                        Bq[k][j] = *reinterpret_cast<const u32x4 *>(
+                            wtt + (((size_t)(n_blk + j * 16 + li) * R + r) * S + s) * C + kc * 32 + lg * 8);
+                    }
                 }
+            };
+            auto ld_f = [&](int kc, int f) {
+                Af[kc][f] = *reinterpret_cast<const u32x4 *>(arow + kc * PLANE + aofs[f]);
+            };
+            auto ld_a = [&](int k) {  // the activation fragments step k needs first
+                const int kc = k / S, s = k - kc * S;
+                if (s == 0) {
+#pragma unroll
+                    for (int f = 0; f < kMT; ++f) ld_f(kc, f);
+                } else {
+                    ld_f(kc, s + kMT - 1);
+                }
+            };
+#pragma unroll
+            for (int k = 0; k < BD && k < NS; ++k) ld_b(k);
+            ld_a(0);
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                if (k + BD < NS) ld_b(k + BD);
+                if (k + 1 < NS) ld_a(k + 1);
+                __builtin_amdgcn_sched_barrier(0);
+                const int kc = k / S, s = k - kc * S;
+#pragma unroll
+                for (int m = 0; m < kMT; ++m)
+#pragma unroll
+                    for (int j = 0; j < NT; ++j)
+                        acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            __builtin_bit_cast(bf16x8, Af[kc][s + m]), __builtin_bit_cast(bf16x8, Bq[k][j]),
+                            acc[m][j], 0, 0, 0);
             }
+        };
+        if constexpr (WROW) {
+            // the next filter row's weights (row 0 of the next tile after the
+            // last row) load from L2 while this row computes; the barrier
+            // after the store keeps the two buffers' readers and writer apart
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const bool nxt = r + 1 < R || more;
+                u32x4 v[RITERS];
+                if (nxt) wrow_load(r + 1 < R ? r + 1 : 0, v);
+                filter_row(r);
+                if (nxt) wrow_store(wb ^ 1, v);
+                if (r + 1 < R) __syncthreads();
+                wb ^= 1;
+            }
+        } else if constexpr (R <= 7) {  // small filters: the whole walk unrolled (no loop-carried accumulator copies)
+#pragma unroll
+            for (int r = 0; r < R; ++r) filter_row(r);
+        } else {
+#pragma unroll 1
+            for (int r = 0; r < R; ++r) filter_row(r);
+        }
+
+        // D[i = 4*lg + e][n = li] of M-tile m: output pixel x0 + 4*i + m
+        const int y = y0 + wave;
+        if (y < a.out_h) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int m = 0; m < kMT; ++m) {
+                    const int x = x0 + 16 * lg + 4 * e + m;
+                    if (x < a.out_w) {
+                        float *dst = a.out + (((size_t)b * a.out_h + y) * a.out_w + x) * a.c_out + n_blk + li;
+#pragma unroll
+                        for (int j = 0; j < NT; ++j) dst[j * 16] = acc[m][j][e];
+                    }
+                }
+        }
+        if (more) {
+            __syncthreads();  // every wave is done with this tile's halo rows
+            if (down) {
+                if constexpr (!PREFETCH) Next::load(a, b, y0 + TH, x0, R - 1, nh);
+                Next::store(halo, y0 + TH, R - 1, nh);
+            } else {  // a new strip: the whole halo
+                int b1, y1, x1;
+                tile_origin(t + 1, b1, y1, x1);
+                u32x4 v[Full::ITERS];
+                Full::load(a, b1, y1, x1, 0, v);
+                Full::store(halo, y1, 0, v);
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -606,6 +706,8 @@ const LdsEntry kLdsTable[] = {
     GT_L(32, 2, 1), GT_L(32, 2, 3), GT_L(32, 2, 5), GT_L(32, 2, 7), GT_L(32, 2, 9), GT_L(32, 2, 17),
 };
 #undef GT_L
+constexpr size_t kLdsTableSize = sizeof(kLdsTable) / sizeof(kLdsTable[0]);
+std::atomic<int> g_lds_occupancy[kLdsTableSize];  // resident workgroups per CU, 0 = not yet queried
 
 // The LDS-staged kernel for (c_in, c_out, f) when instantiated and its halo
 // fits the device's LDS; null otherwise.
@@ -663,10 +765,30 @@ int launch_igemm(const gt_problem &p, const gt_conv_config &, const void *in, co
     if (p.kind == GT_IGEMM_BF16_MFMA && p.filt_h == p.filt_w) {
         if (const LdsEntry *e = lds_kernel_for(p.filt_h, p.c_in, p.c_out)) {
             const int64_t tiles = (int64_t)p.n * ((p.out_h + e->th - 1) / e->th) * ((p.out_w + kLdsTW - 1) / kLdsTW);
-            if (e->lds > 65536)
-                GT_HIP_CHECK(hipFuncSetAttribute(e->fn, hipFuncAttributeMaxDynamicSharedMemorySize, e->lds));
-            dim3 grid((unsigned)tiles, (unsigned)(p.c_out / (16 * e->nt)));
-            GT_HIP_CHECK(hipLaunchKernel(e->fn, grid, dim3(64 * e->th), args, (size_t)e->lds, s));
+            const int gy = p.c_out / (16 * e->nt);
+            const size_t idx = (size_t)(e - kLdsTable);
+            int occ = g_lds_occupancy[idx].load(std::memory_order_relaxed);
+            if (occ == 0) {
+                if (e->lds > 65536)
+                    GT_HIP_CHECK(hipFuncSetAttribute(e->fn, hipFuncAttributeMaxDynamicSharedMemorySize, e->lds));
+                GT_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, e->fn, 64 * e->th, (size_t)e->lds));
+                occ = std::max(1, occ);
+                g_lds_occupancy[idx].store(occ, std::memory_order_relaxed);
+            }
+            // persistent grid: about one resident wave of workgroups, each
+            // taking an equal run of tiles; rounded up to a multiple of 8 for
+            // the XCD-aware order (surplus workgroups find no tiles and exit)
+            const int64_t resident = std::max<int64_t>(1, (int64_t)std::max(1, state().dev.cu_count) * occ / gy);
+            const int64_t m = std::min(tiles, resident);
+            const int64_t per = (tiles + m - 1) / m;
+            int64_t gx = (tiles + per - 1) / per;
+            if (gx >= 8) gx = (gx + 7) / 8 * 8;
+            if (per > INT32_MAX || gx * per >= ((int64_t)1 << 31))
+                return set_error(GT_E_INVAL, "igemm: too many tiles");
+            int tiles_per_wg = (int)per;
+            void *largs[] = {&a, &tiles_per_wg};
+            dim3 grid((unsigned)gx, (unsigned)gy);
+            GT_HIP_CHECK(hipLaunchKernel(e->fn, grid, dim3(64 * e->th), largs, (size_t)e->lds, s));
             return GT_OK;
         }
     }

@@ -90,6 +90,29 @@ def test_igemm_full_size_sampled(gt, f):
         assert np.isfinite(got).all()
 
 
+# Shapes with more tiles than the 256-CU device holds at once, so persistent
+# workgroups run several tiles each, including runs that cross from one
+# column strip (or image) to the next, ragged right and bottom tiles, and each
+# weight placement (all in LDS, one filter row double-buffered, read from L2).
+PERSISTENT_CASES = [  # n, h, w, c_in, c_out, f
+    (4, 150, 250, 64, 64, 3), (3, 146, 190, 64, 64, 5), (3, 146, 190, 32, 64, 9), (3, 146, 190, 64, 64, 7),
+]
+
+
+@pytest.mark.parametrize("case", PERSISTENT_CASES)
+def test_igemm_persistent_runs(gt, case):
+    n, h, w, ci, co, f = case
+    x, wt = conv_inputs(n, h, w, ci, co, f, f, seed=7 + f)
+    pad = (f - 1) // 2
+    ref = oracle.conv_nhwc(x.float().numpy(), wt.float().numpy(), pad, pad)
+    print("case: persistent", case, flush=True)
+    got = run(gt, gt.IGEMM_BF16_MFMA, x, wt, pad)
+    err = oracle.max_rel_err(got, ref)
+    print("max rel err %.3e" % err, flush=True)
+    assert np.isfinite(got).all()
+    assert err <= TOL[1]
+
+
 def test_igemm_unsupported(gt):
     x, wt = conv_inputs(1, 8, 8, 48, 64, 3, 3)
     with pytest.raises(gt.GreentuneError) as e:
