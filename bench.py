@@ -125,8 +125,10 @@ def main():
     if args.probe:
         buf = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         t, g = gt.roofline_probe(buf)
+        m1, m2 = gt.mfma_probe(buf)
         print(json.dumps({"fp32_fma_tflops": t, "copy_gbs": g, "copy_read_bytes_per_launch": 1 << 29,
-                          "copy_write_bytes_per_launch": 1 << 29}), flush=True)
+                          "copy_write_bytes_per_launch": 1 << 29, "bf16_mfma_tflops_1wave_per_simd": m1,
+                          "bf16_mfma_tflops_2waves_per_simd": m2}), flush=True)
         gt.shutdown()
         return
     img, w = xcorr_inputs(4096, 4096, 17, 17, seed=0)

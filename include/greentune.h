@@ -319,6 +319,13 @@ int gt_ffg_centrality(const gt_conv_config *cfgs, const double *fitness, size_t 
 int gt_roofline_probe(void *d_buf, size_t bytes, void *hip_stream, double *fp32_fma_tflops,
                       double *copy_gbs);
 
+/* Measure the issue rate of v_mfma_f32_16x16x32_bf16 (independent chains, no
+ * memory traffic) with one and with two waves per SIMD (one or two 256-thread
+ * workgroups per CU), in TFLOP/s, on hip_stream.  d_buf: caller-owned device
+ * scratch of `bytes` >= 2 KiB per CU (overwritten).  Blocks until done.
+ * Errors: GT_E_INVAL (buffer), GT_E_STATE (no device), GT_E_HIP. */
+int gt_mfma_probe(void *d_buf, size_t bytes, void *hip_stream, double *tflops_1wave, double *tflops_2wave);
+
 #ifdef __cplusplus
 }
 #endif

@@ -142,6 +142,7 @@ def _load():
         "gt_dvfs_state": ([P(Clock)], c_int),
         "gt_fake_sensor_model": ([P(PowerModel), c_double, ctypes.c_uint64], c_int),
         "gt_roofline_probe": ([vp, c_size, vp, P(c_double), P(c_double)], c_int),
+        "gt_mfma_probe": ([vp, c_size, vp, P(c_double), P(c_double)], c_int),
         "gt_batch_pack": ([P(BatchItem), ctypes.c_int32, P(ConvConfig), vp, c_size, P(c_size),
                            P(ctypes.c_int64)], c_int),
         "conv2d_run_batched": ([vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P(ConvConfig),
@@ -168,7 +169,7 @@ EXPORTED = ("gt_init", "gt_shutdown", "gt_last_error", "gt_version", "conv2d_run
             "tune_space_enumerate", "measure_time_energy", "fit_power_model", "gt_power_model_eval", "gt_power_model_throttle_clock",
             "gt_power_model_band", "gt_energy_from_samples", "gt_select", "gt_problem_flops",
             "gt_conv_lds_bytes", "gt_sensor_read", "gt_settable_clocks", "gt_dvfs_state",
-            "gt_fake_sensor_model", "gt_roofline_probe", "gt_batch_pack", "conv2d_run_batched",
+            "gt_fake_sensor_model", "gt_roofline_probe", "gt_mfma_probe", "gt_batch_pack", "conv2d_run_batched",
             "gt_graph_begin", "gt_graph_end", "gt_graph_launch", "gt_graph_destroy", "gt_sampler_start",
             "gt_sampler_stop", "gt_sensor_busy", "gt_ffg_centrality")
 
@@ -376,6 +377,15 @@ def roofline_probe(buf, stream=None):
     _check(_lib.gt_roofline_probe(_ptr(buf), buf.numel() * buf.element_size(), _stream(stream),
                                   ctypes.byref(t), ctypes.byref(g)))
     return t.value, g.value
+
+
+def mfma_probe(buf, stream=None):
+    """BF16 16x16x32 MFMA TFLOP/s with one and with two waves per SIMD (buf:
+    device tensor of >= 2 KiB per CU, overwritten)."""
+    t1, t2 = ctypes.c_double(0), ctypes.c_double(0)
+    _check(_lib.gt_mfma_probe(_ptr(buf), buf.numel() * buf.element_size(), _stream(stream),
+                              ctypes.byref(t1), ctypes.byref(t2)))
+    return t1.value, t2.value
 
 
 # ---- batching ----

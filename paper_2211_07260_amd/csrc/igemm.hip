@@ -246,36 +246,51 @@ __global__ __launch_bounds__(256) void igemm_bf16_mfma_any_kernel(IgemmArgs a, i
 //
 // LDS layout.  Every 32-channel block is a plane of 64-byte pixel records,
 // and chunk c (8 channels) of a record at position pos sits at 16-byte slot
-// c ^ ((pos >> 2) & 3); 16 consecutive positions then cover all 64 banks once,
-// and every fragment read below is 16 consecutive positions of one chunk.
+// c ^ ((pos >> 1) & 3).  Every fragment read below is 16 consecutive records
+// of one chunk; with this swizzle such a read is free of bank conflicts for
+// any starting record (measured with the SQ_LDS_BANK_CONFLICT counter on
+// gfx950, where swizzles by pos & 3 or (pos >> 2) & 3 cost about 4 conflict
+// cycles per read).
 // Halo rows store pixel hx at position (hx & 3) * HW4 + (hx >> 2), so F(t)
 // is 16 consecutive positions.  Weights are stored [r][s][c-block][channel],
 // so a B fragment (16 consecutive output channels) is 16 consecutive records.
 constexpr int kLdsTW = 64;
 constexpr int kRec = 64;  // bytes of one record: 32 BF16 channels
 
-__device__ __forceinline__ int rec_slot(int c, int pos) { return c ^ ((pos >> 2) & 3); }
+__device__ __forceinline__ int rec_slot(int c, int pos) { return c ^ ((pos >> 1) & 3); }
 
 // Where the workgroup's weights live.
-enum WeightMode { kWeightsL2 = 0, kWeightsLds = 1, kWeightsLdsByRow = 2 };
+// (A slab is one filter row of weights for one 32-channel block, or for
+// all of them; the next slab loads from L2 while the current one computes.)
+enum WeightMode { kWeightsL2 = 0, kWeightsLds = 1, kWeightsLdsBySlab = 2, kWeightsLdsByRow = 3 };
 
 // Workgroup shape and LDS use of the staged kernel for (C, NT, F), within
-// 160 KiB: eight output rows with all weights in LDS if that fits; else four
-// rows with all weights, or with one filter row of weights double-buffered
-// (the next row's weights load while the current row computes); else four
-// rows with the weights read from L2.
+// 160 KiB.  Eight output rows (eight waves, two per SIMD: one wave alone
+// issues a 16x16x32 MFMA only every other slot) with all weights in LDS if
+// they fit, else with one-block slabs double-buffered if their fragments fit
+// two waves' registers (NT * F <= 14); else four rows with all weights, with
+// row slabs, or with one-block slabs double-buffered; else four rows with
+// the weights read from L2.
 template <int C, int NT, int F>
 struct LdsPlan {
     static constexpr int kLimit = 163840;
     static constexpr int HW4 = (kLdsTW + F - 1 + 3) / 4;
     static constexpr int halo(int th) { return (th + F - 1) * 4 * HW4 * C * 2; }
     static constexpr int wbytes = 16 * NT * F * F * C * 2;
-    static constexpr int wrow = 16 * NT * F * C * 2;
-    static constexpr int TH = (halo(8) + wbytes <= kLimit) ? 8 : 4;
-    static constexpr int WM = halo(TH) + wbytes <= kLimit       ? kWeightsLds
-                              : halo(TH) + 2 * wrow <= kLimit ? kWeightsLdsByRow
-                                                              : kWeightsL2;
-    static constexpr int bytes = halo(TH) + (WM == kWeightsLds ? wbytes : WM == kWeightsLdsByRow ? 2 * wrow : 0);
+    static constexpr int slab = 16 * NT * F * kRec;  // one filter row, one 32-channel block
+    static constexpr int rslab = slab * (C / 32);    // one filter row, all blocks
+    static constexpr bool fits(int th, int w) { return halo(th) + w <= kLimit; }
+    static constexpr bool T8 = fits(8, wbytes) || (NT * F <= 14 && fits(8, 2 * slab));
+    static constexpr int TH = T8 ? 8 : 4;
+    static constexpr int WM = fits(TH, wbytes)                ? kWeightsLds
+                              : !T8 && fits(TH, 2 * rslab)   ? kWeightsLdsByRow
+                              : fits(TH, 2 * slab)           ? kWeightsLdsBySlab
+                                                             : kWeightsL2;
+    static constexpr int bytes = halo(TH) + (WM == kWeightsLds         ? wbytes
+                                             : WM == kWeightsLdsByRow  ? 2 * rslab
+                                             : WM == kWeightsLdsBySlab ? 2 * slab
+                                                                       : 0);
+    static constexpr int threads = 64 * TH;
 };
 
 // Rows hy0 .. hy0+ROWS-1 of a tile's input halo: chunk k = (pixel p = k / CH,
@@ -288,10 +303,15 @@ struct HaloRows {
     static constexpr int CH = C / 8, KC = C / 32, HW4 = (HW + 3) / 4;
     static constexpr int ROWB = 4 * HW4 * kRec, PLANE = HH * ROWB;
     static constexpr int NCHUNK = ROWS * HW * CH, ITERS = (NCHUNK + NTHR - 1) / NTHR;
-    // every load of a thread is issued before any is used; chunks outside the
-    // image read a valid address and are replaced by zeros
-    __device__ static void load(const IgemmArgs &a, int b, int y0, int x0, int hy0, u32x4 (&v)[ITERS]) {
+    static_assert(ITERS <= 32, "one mask bit per chunk");
+    // Every load of a thread is issued before any is used.  Chunks outside the
+    // image read a valid address and have their bit of *outside set; store()
+    // writes zeros for them.  (Zeroing here would make the thread wait for
+    // the loads, which are meant to stay in flight while a tile computes.)
+    __device__ static void load(const IgemmArgs &a, int b, int y0, int x0, int hy0, u32x4 (&v)[ITERS],
+                                uint32_t &outside) {
         const unsigned short *in = static_cast<const unsigned short *>(a.in);
+        outside = 0;
 #pragma unroll
         for (int it = 0; it < ITERS; ++it) {
             const int k = threadIdx.x + it * NTHR;
@@ -300,11 +320,11 @@ struct HaloRows {
             const int y = y0 - a.ph + hy, x = x0 - a.pw + hx;
             const bool inside = k < NCHUNK && y >= 0 && y < a.h && x >= 0 && x < a.wd;
             const size_t src = inside ? (((size_t)b * a.h + y) * a.wd + x) * C + q * 8 : 0;
-            const u32x4 t = *reinterpret_cast<const u32x4 *>(in + src);
-            v[it] = inside ? t : u32x4{0u, 0u, 0u, 0u};
+            v[it] = *reinterpret_cast<const u32x4 *>(in + src);
+            outside |= inside ? 0u : 1u << it;
         }
     }
-    __device__ static void store(unsigned char *halo, int y0, int hy0, const u32x4 (&v)[ITERS]) {
+    __device__ static void store(unsigned char *halo, int y0, int hy0, const u32x4 (&v)[ITERS], uint32_t outside) {
 #pragma unroll
         for (int it = 0; it < ITERS; ++it) {
             const int k = threadIdx.x + it * NTHR;
@@ -313,7 +333,8 @@ struct HaloRows {
             const int pos = (hx & 3) * HW4 + (hx >> 2);
             if (k < NCHUNK)
                 *reinterpret_cast<u32x4 *>(halo + (q >> 2) * PLANE + slot * ROWB + pos * kRec +
-                                           16 * rec_slot(q & 3, pos)) = v[it];
+                                           16 * rec_slot(q & 3, pos)) =
+                    (outside >> it) & 1 ? u32x4{0u, 0u, 0u, 0u} : v[it];
         }
     }
 };
@@ -327,7 +348,8 @@ struct HaloRows {
 // TH output rows (= waves) per workgroup; WM: weight placement (WeightMode).
 template <int C, int NT, int R, int S, int TH, int WM>
 __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, int tiles_per_wg) {
-    constexpr bool WL = WM == kWeightsLds, WROW = WM == kWeightsLdsByRow;
+    constexpr bool WL = WM == kWeightsLds, WSLAB = WM == kWeightsLdsBySlab || WM == kWeightsLdsByRow;
+    constexpr int NKC = WM == kWeightsLdsBySlab ? 1 : C / 32;  // c-blocks per pass (and per slab)
     constexpr int CH = C / 8, KC = C / 32;
     constexpr int HW = kLdsTW + S - 1, HH = TH + R - 1;
     constexpr int NTHR = TH * 64;
@@ -335,17 +357,28 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
     typedef HaloRows<C, HW, HH, NTHR, TH> Next;
     constexpr int HW4 = Full::HW4, ROWB = Full::ROWB, PLANE = Full::PLANE;
     constexpr int TAPB = 16 * NT * kRec;  // one (tap, c-block) of the workgroup's weights
-    constexpr int WROW_BYTES = S * KC * TAPB;
+    constexpr int SLAB_BYTES = S * NKC * TAPB;    // one slab of weights
     constexpr int WCHUNK = 16 * NT * R * S * CH;  // this workgroup's weight chunks
-    constexpr int RCHUNK = 16 * NT * S * CH;      // ... of one filter row
-    // weight loads from L2 would wait behind the prefetch (loads complete in
-    // order), so that mode loads the next rows after the tile instead
-    constexpr bool PREFETCH = WM != kWeightsL2;
+    constexpr int SCHUNK = 16 * NT * S * NKC * 4; // ... of one slab
+    // The next tile's TH new halo rows replace ring rows this tile has
+    // finished with.  With all weights in LDS they are prefetched into
+    // registers while the tile computes and stored after it.  In slab mode,
+    // whose passes end in barriers, ring row i is free once filter row i is
+    // done: rows i < R-1 are loaded during filter row i and stored at the
+    // start of filter row i+1 (a few registers at a time), the rest during
+    // the last filter row and stored after it.  With weights from L2 (each
+    // weight load would wait behind a prefetch: loads complete in order) the
+    // rows load after the tile.
+    constexpr bool PREFETCH = WM == kWeightsLds;
+    constexpr int PROG = R - 1 < TH ? R - 1 : TH;  // slab mode: ring rows refilled during the tile
+    constexpr int ENDR = TH - PROG;                // ... and at its end
+    typedef HaloRows<C, HW, HH, NTHR, 1> One;
+    typedef HaloRows<C, HW, HH, NTHR, (ENDR > 0 ? ENDR : 1)> EndRows;
     constexpr int BD = WM == kWeightsL2 ? 2 : 1;  // weight fragments are loaded BD steps ahead
     // weights first (offset 0), then the halo planes
     extern __shared__ __align__(16) unsigned char lds[];
     unsigned char *wlds = lds;
-    unsigned char *halo = lds + (WL ? R * S * KC * TAPB : WROW ? 2 * WROW_BYTES : 0);
+    unsigned char *halo = lds + (WL ? R * S * KC * TAPB : WSLAB ? 2 * SLAB_BYTES : 0);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const int tiles_x = (a.out_w + kLdsTW - 1) / kLdsTW, tiles_y = (a.out_h + TH - 1) / TH;
@@ -374,26 +407,31 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
     auto wofs = [&](int tap, int cl, int q) {
         return ((tap * KC + (q >> 2)) * (16 * NT) + cl) * kRec + 16 * rec_slot(q & 3, cl);
     };
-    // one filter row of weights (row-buffered mode): chunk k = (channel cl,
-    // tap s, chunk q) of row r
-    constexpr int RITERS = (RCHUNK + NTHR - 1) / NTHR;
-    auto wrow_load = [&](int r, u32x4(&v)[RITERS]) {
+    // one slab of weights (slab modes): slab z = filter row r = z * NKC / KC,
+    // c-blocks kc0 = z * NKC % KC .. kc0 + NKC - 1; chunk k = (channel cl,
+    // tap s, chunk c of the slab's blocks), stored at (s, block, cl) like the
+    // all-in-LDS layout
+    constexpr int SITERS = (SCHUNK + NTHR - 1) / NTHR;
+    auto wslab_load = [&](int z, u32x4(&v)[SITERS]) {
+        const int r = z * NKC / KC, kc0 = z * NKC - r * KC;
 #pragma unroll
-        for (int it = 0; it < RITERS; ++it) {
+        for (int it = 0; it < SITERS; ++it) {
             const int k = threadIdx.x + it * NTHR;
-            const int cl = k / (S * CH), rem = k - cl * (S * CH);
-            const int sx = rem / CH, q = rem - sx * CH;
+            const int cl = k / (S * NKC * 4), rem = k - cl * (S * NKC * 4);
+            const int sx = rem / (NKC * 4), c = rem - sx * (NKC * 4);
             v[it] = *reinterpret_cast<const u32x4 *>(
-                wt + (k < RCHUNK ? (((size_t)(n_blk + cl) * R + r) * S + sx) * C + q * 8 : 0));
+                wt + (k < SCHUNK ? (((size_t)(n_blk + cl) * R + r) * S + sx) * C + kc0 * 32 + c * 8 : 0));
         }
     };
-    auto wrow_store = [&](int buf, const u32x4(&v)[RITERS]) {
+    auto wslab_store = [&](int buf, const u32x4(&v)[SITERS]) {
 #pragma unroll
-        for (int it = 0; it < RITERS; ++it) {
+        for (int it = 0; it < SITERS; ++it) {
             const int k = threadIdx.x + it * NTHR;
-            const int cl = k / (S * CH), rem = k - cl * (S * CH);
-            const int sx = rem / CH, q = rem - sx * CH;
-            if (k < RCHUNK) *reinterpret_cast<u32x4 *>(wlds + buf * WROW_BYTES + wofs(sx, cl, q)) = v[it];
+            const int cl = k / (S * NKC * 4), rem = k - cl * (S * NKC * 4);
+            const int sx = rem / (NKC * 4), c = rem - sx * (NKC * 4);
+            if (k < SCHUNK)
+                *reinterpret_cast<u32x4 *>(wlds + buf * SLAB_BYTES + ((sx * NKC + (c >> 2)) * (16 * NT) + cl) * kRec +
+                                           16 * rec_slot(c & 3, cl)) = v[it];
         }
     };
 
@@ -401,8 +439,9 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
         int b, y0, x0;
         tile_origin(t_begin, b, y0, x0);
         u32x4 v[Full::ITERS];
-        Full::load(a, b, y0, x0, 0, v);
-        Full::store(halo, y0, 0, v);
+        uint32_t vo;
+        Full::load(a, b, y0, x0, 0, v, vo);
+        Full::store(halo, y0, 0, v, vo);
     }
     if constexpr (WL) {
         // all weights of output channels n_blk .. n_blk + 16*NT, staged once:
@@ -425,11 +464,11 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
             if (k < WCHUNK) *reinterpret_cast<u32x4 *>(wlds + wofs(rs, cl, q)) = v[it];
         }
     }
-    int wb = 0;  // row-buffered mode: the LDS buffer holding the current filter row
-    if constexpr (WROW) {
-        u32x4 v[RITERS];
-        wrow_load(0, v);
-        wrow_store(0, v);
+    int wb = 0;  // slab mode: the LDS buffer holding the current slab
+    if constexpr (WSLAB) {
+        u32x4 v[SITERS];
+        wslab_load(0, v);
+        wslab_store(0, v);
     }
     __syncthreads();
 
@@ -443,6 +482,34 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
     }
     const int bofs = li * kRec + 16 * rec_slot(lg, li);
 
+    // The reduction of a tile runs as NZ passes: a pass is one filter row
+    // (all c-blocks), or in slab mode one slab (one c-block of a row).
+    constexpr int NZ = R * KC / NKC;     // passes per tile
+    constexpr int NS = NKC * S;          // steps per pass
+    constexpr bool UNROLLED = WSLAB || R <= 7;
+    // Deferred output stores: with the passes unrolled, the weights in LDS
+    // and one wave per SIMD (registers to spare), a tile's results stay in
+    // registers and are stored during the next tile's first passes, instead
+    // of every workgroup storing at once at its tile end while the matrix
+    // cores idle.  (With weights read from L2, each weight load would wait
+    // behind the stores: loads and stores share one in-order counter.)
+    constexpr bool DEFER = UNROLLED && WM != kWeightsL2 && TH == 4 && NZ <= 10 && S <= 7;
+    constexpr int NQ = kMT * NT;              // 16-byte stores per lane and tile
+    constexpr int ZS = NZ < 4 ? NZ : 4;        // passes they are spread over
+    constexpr int QPZ = (NQ + ZS - 1) / ZS;    // ... per pass
+    constexpr int QPS = (QPZ + NS - 1) / NS;   // ... per step
+    // with deferred stores, the next tile's halo rows are prefetched halfway
+    // through pass PF_Z (else at the tile start)
+    constexpr int PF_Z = NZ >= 2 ? NZ - 2 : 0;
+    f32x4 sv[kMT][NT];
+    bool pending = false;  // sv holds a tile's results still to be stored (wave-uniform)
+    float *sv_dst = a.out;
+    int sv_xl = 0;  // M-tiles m < sv_xl of this lane are inside the output row
+    auto store_q = [&](int q) {
+        const int m = q / NT, j = q - m * NT;
+        if (m < sv_xl) *reinterpret_cast<f32x4 *>(sv_dst + (size_t)m * a.c_out + 16 * j) = sv[m][j];
+    };
+
     for (int t = t_begin; t < t_end; ++t) {
         const bool more = t + 1 < t_end;                   // uniform over the workgroup
         const bool down = more && (t + 1) % tiles_y != 0;  // the next tile is the one below
@@ -450,8 +517,9 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
         tile_origin(t, b, y0, x0);
         // the next tile's TH new rows: its halo rows R-1 .. R+TH-2
         u32x4 nh[Next::ITERS];
-        if constexpr (PREFETCH)
-            if (down) Next::load(a, b, y0 + TH, x0, R - 1, nh);
+        uint32_t nho = 0;
+        if constexpr (PREFETCH && !DEFER)
+            if (down) Next::load(a, b, y0 + TH, x0, R - 1, nh, nho);
         // opaque per tile, so weight loads from L2 are not hoisted out of the tile loop
         const unsigned short *wtt = wt;
         asm volatile("" : "+s"(wtt));
@@ -462,38 +530,55 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
 #pragma unroll
             for (int j = 0; j < NT; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-        // One filter row: steps k = (c-block kc, tap s), s fastest.  Step k
-        // uses F(s) .. F(s+kMT-1) of block kc and the weights of (r, s, kc);
-        // the activation fragments a step newly needs are loaded one step
-        // ahead, the weight fragments BD steps ahead.
-        auto filter_row = [&](int r) {
-            constexpr int NS = KC * S;
+        // work slotted between the steps of unrolled passes: deferred stores
+        // of the previous tile and the halo prefetch
+        auto hook = [&](int z, int k) {
+            if constexpr (DEFER) {
+                if (pending) {
+#pragma unroll
+                    for (int i = 0; i < QPS; ++i) {
+                        const int q = z * QPZ + k * QPS + i;
+                        if (z < ZS && k * QPS + i < QPZ && q < NQ) store_q(q);
+                    }
+                }
+                if constexpr (PREFETCH)
+                    if (z == PF_Z && k == NS / 2 && down) Next::load(a, b, y0 + TH, x0, R - 1, nh, nho);
+            }
+        };
+
+        // Pass z = (filter row r, first c-block kc0): steps k = (c-block
+        // kc0 + k / S, tap k % S).  Step k uses F(s) .. F(s+kMT-1) of its
+        // c-block and the weights of (r, s, c-block); the activation
+        // fragments a step newly needs are loaded one step ahead, the weight
+        // fragments BD steps ahead.  mid() runs halfway.
+        auto pass = [&](int z, auto &&mid) {
+            const int r = z * NKC / KC, kc0 = z * NKC - r * KC;
             const unsigned char *arow = halo + ((y0 + wave + r) % HH) * ROWB;
-            u32x4 Af[KC][kMT + S - 1], Bq[NS][NT];
+            u32x4 Af[NKC][kMT + S - 1], Bq[NS][NT];
             auto ld_b = [&](int k) {
-                const int kc = k / S, s = k - kc * S;
+                const int kk = k / S, s = k - kk * S, kc = kc0 + kk;
 #pragma unroll
                 for (int j = 0; j < NT; ++j) {
                     if constexpr (WL) {
                         Bq[k][j] = *reinterpret_cast<const u32x4 *>(wlds + ((r * S + s) * KC + kc) * TAPB + j * 16 * kRec + bofs);
-                    } else if constexpr (WROW) {
-                        Bq[k][j] = *reinterpret_cast<const u32x4 *>(wlds + wb * WROW_BYTES + (s * KC + kc) * TAPB + j * 16 * kRec + bofs);
+                    } else if constexpr (WSLAB) {
+                        Bq[k][j] = *reinterpret_cast<const u32x4 *>(wlds + wb * SLAB_BYTES + (s * NKC + kk) * TAPB + j * 16 * kRec + bofs);
                     } else {
                         Bq[k][j] = *reinterpret_cast<const u32x4 *>(
                             wtt + (((size_t)(n_blk + j * 16 + li) * R + r) * S + s) * C + kc * 32 + lg * 8);
                     }
                 }
             };
-            auto ld_f = [&](int kc, int f) {
-                Af[kc][f] = *reinterpret_cast<const u32x4 *>(arow + kc * PLANE + aofs[f]);
+            auto ld_f = [&](int kk, int f) {
+                Af[kk][f] = *reinterpret_cast<const u32x4 *>(arow + (kc0 + kk) * PLANE + aofs[f]);
             };
             auto ld_a = [&](int k) {  // the activation fragments step k needs first
-                const int kc = k / S, s = k - kc * S;
+                const int kk = k / S, s = k - kk * S;
                 if (s == 0) {
 #pragma unroll
-                    for (int f = 0; f < kMT; ++f) ld_f(kc, f);
+                    for (int f = 0; f < kMT; ++f) ld_f(kk, f);
                 } else {
-                    ld_f(kc, s + kMT - 1);
+                    ld_f(kk, s + kMT - 1);
                 }
             };
 #pragma unroll
@@ -501,67 +586,96 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
             ld_a(0);
 #pragma unroll
             for (int k = 0; k < NS; ++k) {
+                if (k == NS / 2) mid();  // the caller's LDS stores, while earlier MFMAs drain
+                hook(z, k);
                 if (k + BD < NS) ld_b(k + BD);
                 if (k + 1 < NS) ld_a(k + 1);
                 __builtin_amdgcn_sched_barrier(0);
-                const int kc = k / S, s = k - kc * S;
+                const int kk = k / S, s = k - kk * S;
+                // weights as the MFMA's A operand and activations as B, so the
+                // accumulator holds D[channel][pixel]: a lane's 4 results are 4
+                // consecutive channels of one pixel (one 16-byte store)
 #pragma unroll
                 for (int m = 0; m < kMT; ++m)
 #pragma unroll
                     for (int j = 0; j < NT; ++j)
                         acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                            __builtin_bit_cast(bf16x8, Af[kc][s + m]), __builtin_bit_cast(bf16x8, Bq[k][j]),
+                            __builtin_bit_cast(bf16x8, Bq[k][j]), __builtin_bit_cast(bf16x8, Af[kk][s + m]),
                             acc[m][j], 0, 0, 0);
             }
         };
-        if constexpr (WROW) {
-            // the next filter row's weights (row 0 of the next tile after the
-            // last row) load from L2 while this row computes; the barrier
-            // after the store keeps the two buffers' readers and writer apart
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const bool nxt = r + 1 < R || more;
-                u32x4 v[RITERS];
-                if (nxt) wrow_load(r + 1 < R ? r + 1 : 0, v);
-                filter_row(r);
-                if (nxt) wrow_store(wb ^ 1, v);
-                if (r + 1 < R) __syncthreads();
+        auto nothing = [] {};
+        u32x4 pv[One::ITERS], ev[EndRows::ITERS];  // slab mode: refill rows in flight
+        uint32_t po = 0, eo = 0;
+        if constexpr (WSLAB) {
+            // the next slab (slab 0 of the next tile after the last) loads
+            // from L2 while this one computes and is stored halfway through
+            // it; the barrier after each slab keeps the two buffers' readers
+            // and writer apart
+            auto slab = [&](int z) {
+                const bool nxt = z + 1 < NZ || more;
+                const int r = z * NKC / KC;
+                if (z * NKC - r * KC == 0 && down) {  // the first pass of filter row r
+                    if (r >= 1 && r - 1 < PROG) One::store(halo, y0 + TH, R - 1 + (r - 1), pv, po);
+                    if (r < PROG) One::load(a, b, y0 + TH, x0, R - 1 + r, pv, po);
+                    if (ENDR > 0 && r == R - 1) EndRows::load(a, b, y0 + TH, x0, R - 1 + PROG, ev, eo);
+                }
+                u32x4 v[SITERS];
+                if (nxt) wslab_load(z + 1 < NZ ? z + 1 : 0, v);
+                pass(z, [&] {
+                    if (nxt) wslab_store(wb ^ 1, v);
+                });
+                if (z + 1 < NZ) __syncthreads();
                 wb ^= 1;
+            };
+            if constexpr (DEFER) {  // the deferred-store slots need compile-time pass indices
+#pragma unroll
+                for (int z = 0; z < NZ; ++z) slab(z);
+            } else {  // two waves per SIMD: keep the code (and its registers) to one pass
+#pragma unroll 1
+                for (int z = 0; z < NZ; ++z) slab(z);
             }
         } else if constexpr (R <= 7) {  // small filters: the whole walk unrolled (no loop-carried accumulator copies)
 #pragma unroll
-            for (int r = 0; r < R; ++r) filter_row(r);
+            for (int z = 0; z < NZ; ++z) pass(z, nothing);
         } else {
 #pragma unroll 1
-            for (int r = 0; r < R; ++r) filter_row(r);
+            for (int z = 0; z < NZ; ++z) pass(z, nothing);
         }
 
-        // D[i = 4*lg + e][n = li] of M-tile m: output pixel x0 + 4*i + m
+        // D[i = 4*lg + e][n = li] of tiles (m, j): output channel n_blk +
+        // 16*j + 4*lg + e of pixel x0 + 4*li + m
         const int y = y0 + wave;
-        if (y < a.out_h) {
+        pending = y < a.out_h;
+        sv_dst = a.out + (((size_t)b * a.out_h + y) * a.out_w + x0 + 4 * li) * a.c_out + n_blk + 4 * lg;
+        sv_xl = min(kMT, a.out_w - (x0 + 4 * li));
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
+        for (int m = 0; m < kMT; ++m)
 #pragma unroll
-                for (int m = 0; m < kMT; ++m) {
-                    const int x = x0 + 16 * lg + 4 * e + m;
-                    if (x < a.out_w) {
-                        float *dst = a.out + (((size_t)b * a.out_h + y) * a.out_w + x) * a.c_out + n_blk + li;
+            for (int j = 0; j < NT; ++j) sv[m][j] = acc[m][j];
+        if (!DEFER || !more) {
+            if (pending) {
 #pragma unroll
-                        for (int j = 0; j < NT; ++j) dst[j * 16] = acc[m][j][e];
-                    }
-                }
+                for (int q = 0; q < NQ; ++q) store_q(q);
+            }
+            pending = false;
         }
         if (more) {
             __syncthreads();  // every wave is done with this tile's halo rows
             if (down) {
-                if constexpr (!PREFETCH) Next::load(a, b, y0 + TH, x0, R - 1, nh);
-                Next::store(halo, y0 + TH, R - 1, nh);
+                if constexpr (WSLAB) {
+                    if constexpr (ENDR > 0) EndRows::store(halo, y0 + TH, R - 1 + PROG, ev, eo);
+                } else {
+                    if constexpr (!PREFETCH) Next::load(a, b, y0 + TH, x0, R - 1, nh, nho);
+                    Next::store(halo, y0 + TH, R - 1, nh, nho);
+                }
             } else {  // a new strip: the whole halo
                 int b1, y1, x1;
                 tile_origin(t + 1, b1, y1, x1);
                 u32x4 v[Full::ITERS];
-                Full::load(a, b1, y1, x1, 0, v);
-                Full::store(halo, y1, 0, v);
+                uint32_t vo;
+                Full::load(a, b1, y1, x1, 0, v, vo);
+                Full::store(halo, y1, 0, v, vo);
             }
             __syncthreads();
         }
@@ -694,11 +808,11 @@ const void *valu_kernel_for(int f, int c) {
 struct LdsEntry {
     int c, nt, f;
     const void *fn;
-    int lds, th;
+    int lds, th, threads;
 };
 #define GT_L(C, NT, F)                                                                                     \
     {C, NT, F, (const void *)&igemm_bf16_lds_kernel<C, NT, F, F, LdsPlan<C, NT, F>::TH, LdsPlan<C, NT, F>::WM>, \
-     LdsPlan<C, NT, F>::bytes, LdsPlan<C, NT, F>::TH}
+     LdsPlan<C, NT, F>::bytes, LdsPlan<C, NT, F>::TH, LdsPlan<C, NT, F>::threads}
 const LdsEntry kLdsTable[] = {
     GT_L(64, 4, 1), GT_L(64, 4, 3), GT_L(64, 4, 5), GT_L(64, 4, 7), GT_L(64, 4, 9),
     GT_L(64, 2, 1), GT_L(64, 2, 3), GT_L(64, 2, 5), GT_L(64, 2, 7), GT_L(64, 2, 9),
@@ -762,7 +876,7 @@ int launch_igemm(const gt_problem &p, const gt_conv_config &, const void *in, co
     a.pw = p.pad_w;
     a.m_total = p.n * p.out_h * p.out_w;
     void *args[] = {&a};
-    if (p.kind == GT_IGEMM_BF16_MFMA && p.filt_h == p.filt_w) {
+    if (p.kind == GT_IGEMM_BF16_MFMA && p.filt_h == p.filt_w && ((uintptr_t)out & 15) == 0) {
         if (const LdsEntry *e = lds_kernel_for(p.filt_h, p.c_in, p.c_out)) {
             const int64_t tiles = (int64_t)p.n * ((p.out_h + e->th - 1) / e->th) * ((p.out_w + kLdsTW - 1) / kLdsTW);
             const int gy = p.c_out / (16 * e->nt);
@@ -771,7 +885,7 @@ int launch_igemm(const gt_problem &p, const gt_conv_config &, const void *in, co
             if (occ == 0) {
                 if (e->lds > 65536)
                     GT_HIP_CHECK(hipFuncSetAttribute(e->fn, hipFuncAttributeMaxDynamicSharedMemorySize, e->lds));
-                GT_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, e->fn, 64 * e->th, (size_t)e->lds));
+                GT_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, e->fn, e->threads, (size_t)e->lds));
                 occ = std::max(1, occ);
                 g_lds_occupancy[idx].store(occ, std::memory_order_relaxed);
             }
@@ -788,7 +902,7 @@ int launch_igemm(const gt_problem &p, const gt_conv_config &, const void *in, co
             int tiles_per_wg = (int)per;
             void *largs[] = {&a, &tiles_per_wg};
             dim3 grid((unsigned)gx, (unsigned)gy);
-            GT_HIP_CHECK(hipLaunchKernel(e->fn, grid, dim3(64 * e->th), largs, (size_t)e->lds, s));
+            GT_HIP_CHECK(hipLaunchKernel(e->fn, grid, dim3(e->threads), largs, (size_t)e->lds, s));
             return GT_OK;
         }
     }

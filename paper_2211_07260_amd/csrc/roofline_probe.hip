@@ -1,6 +1,7 @@
 // Roofline probes: the achievable FP32 vector FMA rate (the same
 // v_fmac_f32 acc, s_w, v_in form the convolution issues, packed FP32
-// disabled) and the HBM copy bandwidth, measured on the device at hand.
+// disabled), the HBM copy bandwidth, and the BF16 MFMA issue rate with one
+// and two waves per SIMD, measured on the device at hand.
 #include <hip/hip_runtime.h>
 
 #include "gt_internal.hpp"
@@ -26,6 +27,30 @@ __global__ __launch_bounds__(256) void fma_peak_kernel(float *out, const float *
     float t = 0.0f;
 #pragma unroll
     for (int k = 0; k < 32; ++k) t += acc[k];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = t;
+}
+
+// 16 independent 16x16x32 BF16 MFMA chains per wave (no loads): the matrix
+// cores' issue rate for this instruction.
+__global__ __launch_bounds__(256) void mfma_peak_kernel(float *out, int iters) {
+    typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
+    f32x4 acc[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 x, y;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        x[k] = (__bf16)(1e-3f * (float)(threadIdx.x + k));
+        y[k] = (__bf16)(1e-3f * (float)k);
+    }
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, acc[k], 0, 0, 0);
+    }
+    float t = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) t += acc[k][0] + acc[k][1] + acc[k][2] + acc[k][3];
     out[blockIdx.x * blockDim.x + threadIdx.x] = t;
 }
 
@@ -77,6 +102,37 @@ extern "C" int gt_roofline_probe(void *d_buf, size_t bytes, void *hip_stream, do
     GT_HIP_CHECK(hipEventSynchronize(b));
     GT_HIP_CHECK(hipEventElapsedTime(&ms, a, b));
     *copy_gbs = 2.0 * (double)n4 * 16 * reps / (ms * 1e-3) / 1e9;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return GT_OK;
+}
+
+extern "C" int gt_mfma_probe(void *d_buf, size_t bytes, void *hip_stream, double *tflops_1wave,
+                             double *tflops_2wave) {
+    clear_error();
+    if (!d_buf || !tflops_1wave || !tflops_2wave) return set_error(GT_E_INVAL, "gt_mfma_probe: null argument");
+    if (!state().inited || (state().flags & GT_INIT_HOST_ONLY))
+        return set_error(GT_E_STATE, "gt_mfma_probe: needs gt_init on a device");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int cus = state().dev.cu_count > 0 ? state().dev.cu_count : 256;
+    const int iters = 4000;
+    if ((size_t)cus * 2 * 256 * sizeof(float) > bytes) return set_error(GT_E_INVAL, "gt_mfma_probe: buffer too small");
+    float *out = static_cast<float *>(d_buf);
+    hipEvent_t a, b;
+    GT_HIP_CHECK(hipEventCreate(&a));
+    GT_HIP_CHECK(hipEventCreate(&b));
+    double *res[2] = {tflops_1wave, tflops_2wave};
+    for (int w = 1; w <= 2; ++w) {  // w workgroups of 4 waves per CU: w waves per SIMD
+        const int blocks = cus * w;
+        hipLaunchKernelGGL(mfma_peak_kernel, dim3(blocks), dim3(256), 0, s, out, 16);  // warm
+        GT_HIP_CHECK(hipEventRecord(a, s));
+        hipLaunchKernelGGL(mfma_peak_kernel, dim3(blocks), dim3(256), 0, s, out, iters);
+        GT_HIP_CHECK(hipEventRecord(b, s));
+        GT_HIP_CHECK(hipEventSynchronize(b));
+        float ms = 0;
+        GT_HIP_CHECK(hipEventElapsedTime(&ms, a, b));
+        *res[w - 1] = 16384.0 * 16.0 * iters * (double)blocks * 4 / (ms * 1e-3) / 1e12;
+    }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     return GT_OK;

@@ -54,12 +54,15 @@ def test_batched_equals_single_launch(gt, f, cfg):
             assert oracle.max_rel_err(do.cpu().numpy(), ref) <= 1e-5
 
 
-def test_batched_small_grid_strides(gt):
+@pytest.mark.parametrize("grid", [7, 16, 24])
+def test_batched_small_grid_strides(gt, grid):
     # a grid far smaller than the tile count: every workgroup walks many tiles
+    # (7: one stride over the whole list; 16, 24: per-XCD contiguous eighths)
     convs, hosts = make_batch(17, 9, seed=3)
     cfg = (32, 4, 4, 4, 0, 0)
     b = gt.Batch(convs, cfg)
-    b.run(grid_blocks=7)
+    print("case: batched grid=%d" % grid, flush=True)
+    b.run(grid_blocks=grid)
     torch.cuda.synchronize()
     for k, (di, dw, do, oh, ow, f) in enumerate(convs):
         ref = oracle.xcorr2d(hosts[k][0].numpy(), hosts[k][1].numpy())

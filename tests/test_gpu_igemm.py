@@ -92,10 +92,12 @@ def test_igemm_full_size_sampled(gt, f):
 
 # Shapes with more tiles than the 256-CU device holds at once, so persistent
 # workgroups run several tiles each, including runs that cross from one
-# column strip (or image) to the next, ragged right and bottom tiles, and each
-# weight placement (all in LDS, one filter row double-buffered, read from L2).
+# column strip (or image) to the next, ragged right and bottom tiles, each
+# weight placement (all in LDS, one slab double-buffered, read from L2) and
+# both workgroup heights (four and eight output rows).
 PERSISTENT_CASES = [  # n, h, w, c_in, c_out, f
     (4, 150, 250, 64, 64, 3), (3, 146, 190, 64, 64, 5), (3, 146, 190, 32, 64, 9), (3, 146, 190, 64, 64, 7),
+    (3, 146, 190, 64, 64, 9), (3, 146, 190, 64, 32, 7),
 ]
 
 
@@ -111,6 +113,21 @@ def test_igemm_persistent_runs(gt, case):
     print("max rel err %.3e" % err, flush=True)
     assert np.isfinite(got).all()
     assert err <= TOL[1]
+
+
+def test_igemm_unaligned_output(gt):
+    # an output that is not 16-byte aligned takes the global-load kernel (4-byte stores)
+    x, wt = conv_inputs(1, 20, 30, 64, 64, 3, 3, seed=21)
+    ref = oracle.conv_nhwc(x.float().numpy(), wt.float().numpy(), 1, 1)
+    dev = torch.device("cuda:0")
+    dx, dw = x.to(dev).contiguous(), wt.to(dev).contiguous()
+    buf = torch.full((1 + 20 * 30 * 64,), float("nan"), dtype=torch.float32, device=dev)
+    out = buf[1:].view(1, 20, 30, 64)
+    assert out.data_ptr() % 16 != 0
+    gt.conv2d_run(gt.Problem(gt.IGEMM_BF16_MFMA, 1, 64, 64, 20, 30, 3, 3, 1, 1), (64, 1, 1, 1, 0, 0), dx, dw, out)
+    torch.cuda.synchronize()
+    assert torch.isnan(buf[:1]).all()
+    assert oracle.max_rel_err(out.cpu().numpy(), ref) <= TOL[1]
 
 
 def test_igemm_unsupported(gt):
