@@ -222,6 +222,65 @@ def exhaustive_clock_search(measure, configs, settable):
     return {"rows": rows, "best": best, "points_measured": len(rows)}
 
 
+# ---- the tuning methods compared in the experiments (section VI.A) ----
+
+METHODS = ("race_to_idle", "energy_to_solution_maxclock", "race_to_idle_clocks", "energy_to_solution_clocks",
+           "global_energy_to_solution")
+
+
+def tuning_methods(measure, configs, settable, f_base=None):
+    """The five ways of choosing a (config, clock) the paper compares:
+
+    * race_to_idle: the fastest (config, clock) over the whole space;
+    * energy_to_solution_maxclock: the lowest-energy config at the top clock;
+    * race_to_idle_clocks: the fastest config at the top clock, then the
+      lowest-energy clock for that config;
+    * energy_to_solution_clocks: the lowest-energy config at the base clock
+      f_base, then the lowest-energy clock for that config;
+    * global_energy_to_solution: the lowest-energy (config, clock) overall.
+
+    Ties go to the other objective, then to the earlier config and lower
+    clock (the library's gt_select order).  Each (config, clock) is measured
+    at most once and shared between methods; 'points' counts what a method
+    needs on its own.  f_base defaults to the top clock (the device's default
+    clock; MI355X publishes no separate base clock) and is snapped to the
+    nearest settable clock.  measure(config, clock_mhz) -> dict with t_run_s
+    and e_run_j.  Returns {method: {"config", "clock_mhz", "t_run_s",
+    "e_run_j", ..., "points"}} plus the measured table under "rows"."""
+    s = sorted(float(f) for f in settable)
+    cfgs = [tuple(gt.as_config(c).as_tuple()) for c in configs]
+    f_max = s[-1]
+    f_b = f_max if f_base is None else min(s, key=lambda f: (abs(f - f_base), f))
+    table = {}
+
+    def get(c, f):
+        key = (c, f)
+        if key not in table:
+            table[key] = {"config": list(c), "clock_mhz": f, **measure(c, f)}
+        return table[key]
+
+    def pick(rows, objective):
+        recs = [{"t_run_s": r["t_run_s"], "e_run_j": r["e_run_j"]} for r in rows]
+        return rows[gt.select(recs, objective)]
+
+    everything = [get(c, f) for c in cfgs for f in s]
+    at_max = [get(c, f_max) for c in cfgs]
+    at_base = [get(c, f_b) for c in cfgs]
+    c_t = tuple(pick(at_max, "time")["config"])
+    c_e = tuple(pick(at_base, "energy")["config"])
+    n_all, n_c, n_f = len(everything), len(cfgs), len(s)
+    out = {
+        "race_to_idle": dict(pick(everything, "time"), points=n_all),
+        "energy_to_solution_maxclock": dict(pick(at_max, "energy"), points=n_c),
+        "race_to_idle_clocks": dict(pick([get(c_t, f) for f in s], "energy"), points=n_c + n_f - 1),
+        "energy_to_solution_clocks": dict(pick([get(c_e, f) for f in s], "energy"), points=n_c + n_f - 1),
+        "global_energy_to_solution": dict(pick(everything, "energy"), points=n_all),
+    }
+    out["rows"] = list(table.values())
+    out["base_clock_mhz"] = f_b
+    return out
+
+
 def hardware_measure(problem, d_in, d_w, d_out, window_s=1.0, discard_s=0.3):
     """measure(config, clock) over the real DVFS knob (needs privileges)."""
     def measure(cfg, f_mhz):

@@ -72,3 +72,33 @@ def test_fake_measurement_and_steered_fit(gt):
         assert rep["band_mhz"] and len(rep["band_mhz"]) < len(settable)
     finally:
         gt.shutdown()
+
+
+def test_fake_dvfs_tuning_methods(gt):
+    # the five methods over 2 configs x 4 clocks through the real measurement
+    # loop: with the fake power model and run time ~ clock-independent (the
+    # clock is not really changed), each pick must still follow its rule
+    from paper_2211_07260_amd import tuner
+    gt.init(0, gt.INIT_FAKE_SENSOR | gt.INIT_FAKE_DVFS)
+    try:
+        m = gt.power_model(MODEL["p_idle"], MODEL["alpha"], MODEL["beta"], MODEL["tau"], MODEL["p_max"])
+        gt.fake_sensor_model(m, noise_w=0.0)
+        img, w, out = bufs(side=512)
+        prob = gt.xcorr_problem(512, 512, 17, 17)
+        cfgs = [(32, 8, 4, 2, 0, 0), (16, 16, 4, 4, 1, 0)]
+        calls = []
+
+        def measure(c, f):
+            calls.append((tuple(c), f))
+            return gt.measure_time_energy(prob, c, img, w, out, gt.clock(gt.CLOCK_SCLK_MHZ, int(f)),
+                                          window_s=0.05, discard_s=0.01)
+        rep = tuner.tuning_methods(measure, cfgs, [800.0, 1200.0, 1600.0, 2000.0])
+        assert len(calls) == 8
+        for name in tuner.METHODS:
+            r = rep[name]
+            assert r["sclk_req_mhz"] == r["clock_mhz"]
+            assert r["p_median_w"] == pytest.approx(gt.power_model_eval(m, r["clock_mhz"]), rel=1e-12)
+        best = min(rep["rows"], key=lambda r: (r["e_run_j"], r["t_run_s"]))
+        assert rep["global_energy_to_solution"]["e_run_j"] == best["e_run_j"]
+    finally:
+        gt.shutdown()
