@@ -4,17 +4,18 @@
 //
 // with NHWC activations, KRSC weights and an NHWC FP32 output.  Seen as a
 // GEMM, M = batch*out_h*out_w output pixels, N = c_out, and the reduction runs
-// over (r, s, c).  Two kernels:
+// over (r, s, c).  The kernels:
 //
 // * BF16 on MFMA (v_mfma_f32_16x16x32_bf16, FP32 accumulate).  A fragment
 //   lane l holds A[m = l%16][k = 8*(l/16) .. +8]: with NHWC input that is 16
 //   contiguous bytes of one pixel's channels, and the KRSC weight fragment
 //   B[k = 8*(l/16) .. +8][n = l%16] is likewise 16 contiguous bytes, so both
-//   operands are loaded straight from memory with one 16-byte load per lane
-//   and no transposition.  A wave owns 4 M-tiles (64 pixels) x NT N-tiles
-//   (16*NT output channels); the fragments of the next (r, s, c-block) step
-//   are loaded while the current step's MFMAs issue.  Zero padding is a
-//   masked load (the address is clamped in bounds, the value replaced by 0).
+//   operands are loaded with one 16-byte load per lane and no transposition.
+//   The main kernel (igemm_bf16_lds_kernel, below) stages the input halo and
+//   the weights in LDS and runs persistent workgroups; a global-load kernel
+//   (a wave owns 4 M-tiles (64 pixels) x NT N-tiles, the next step's
+//   fragments loaded while the current step's MFMAs issue, zero padding as a
+//   masked load) serves the shapes the LDS kernel does not cover.
 //
 // * FP32 on the vector ALUs, the comparison path.  Lanes are output channels
 //   (64 per wave) and a wave owns P pixels, so an input value is the same for
