@@ -98,7 +98,34 @@ def lookup(store, f, side):
     return tuple(table[str(b)]["config"])
 
 
+def time_bucket(f, side, reps=50, store=None):
+    """Time the stored config of one (filter, side) bucket on its tuning batch
+    (about 16 M output pixels of equal-size convolutions), as one persistent
+    launch per repetition.  Returns a dict with the config, ms per launch and
+    TFLOP/s."""
+    import torch
+    dev = torch.device("cuda:0")
+    cfg = lookup(store if store is not None else load(), f, side)
+    n = batch_count(side)
+    ins = torch.rand(n, side + f - 1, side + f - 1, device=dev)
+    w = torch.rand(f, f, device=dev)
+    outs = torch.empty(n, side, side, device=dev)
+    b = gt.Batch([(ins[k], w, outs[k], side, side, f) for k in range(n)], cfg)
+    t = time_batch(b, reps)
+    flops = 2.0 * n * side * side * f * f
+    return {"filter": f, "side": side, "batch": n, "config": list(cfg), "ms": t * 1e3, "tflops": flops / t / 1e12}
+
+
 if __name__ == "__main__":
+    import argparse
+    ap = argparse.ArgumentParser(description="per-size autotuner for the batched launch")
+    ap.add_argument("--time", nargs=2, type=int, metavar=("FILTER", "SIDE"),
+                    help="time the stored config of one bucket instead of tuning")
+    ap.add_argument("--reps", type=int, default=50)
+    args = ap.parse_args()
     gt.init(0, 0)
-    save(tune())
+    if args.time:
+        print(json.dumps(time_bucket(args.time[0], args.time[1], args.reps)), flush=True)
+    else:
+        save(tune())
     gt.shutdown()
