@@ -25,6 +25,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <type_traits>
 
 #include "gt_internal.hpp"
 
@@ -264,45 +265,61 @@ __device__ __forceinline__ int rec_slot(int c, int pos) { return c ^ ((pos >> 1)
 // (A slab is one filter row of weights for one 32-channel block, or for
 // all of them; the next slab loads from L2 while the current one computes.)
 enum WeightMode { kWeightsL2 = 0, kWeightsLds = 1, kWeightsLdsBySlab = 2, kWeightsLdsByRow = 3 };
+// Added to a slab mode: the halo streams through TH+1 rows instead of being
+// kept whole as a ring.
+constexpr int kHaloStream = 4;
 
 // Workgroup shape and LDS use of the staged kernel for (C, NT, F), within
 // 160 KiB.  Eight output rows (eight waves, two per SIMD: one wave alone
-// issues a 16x16x32 MFMA only every other slot) with all weights in LDS if
-// they fit, else with one-block slabs double-buffered if their fragments fit
-// two waves' registers (NT * F <= 14); else four rows with all weights, with
-// row slabs, or with one-block slabs double-buffered; else four rows with
-// the weights read from L2.
+// issues a 16x16x32 MFMA only every other slot) are preferred: with all
+// weights in LDS (and the halo as a ring), else with weight slabs
+// double-buffered (and the halo streamed through TH+1 rows) when the slab's
+// fragments fit two waves' registers; a slab is one filter row for all
+// 32-channel blocks, or for one.  Otherwise the same choices with four rows;
+// last, four rows with the weights read from L2.
 template <int C, int NT, int F>
 struct LdsPlan {
     static constexpr int kLimit = 163840;
     static constexpr int HW4 = (kLdsTW + F - 1 + 3) / 4;
-    static constexpr int halo(int th) { return (th + F - 1) * 4 * HW4 * C * 2; }
+    static constexpr int rowb = 4 * HW4 * C * 2;        // one halo row, all channels
+    static constexpr int ring(int th) { return (th + F - 1) * rowb; }
+    static constexpr int strm(int th) { return (th + 1) * rowb; }
     static constexpr int wbytes = 16 * NT * F * F * C * 2;
     static constexpr int slab = 16 * NT * F * kRec;  // one filter row, one 32-channel block
     static constexpr int rslab = slab * (C / 32);    // one filter row, all blocks
-    static constexpr bool fits(int th, int w) { return halo(th) + w <= kLimit; }
-    static constexpr bool T8 = fits(8, wbytes) || (NT * F <= 14 && fits(8, 2 * slab));
-    static constexpr int TH = T8 ? 8 : 4;
-    static constexpr int WM = fits(TH, wbytes)                ? kWeightsLds
-                              : !T8 && fits(TH, 2 * rslab)   ? kWeightsLdsByRow
-                              : fits(TH, 2 * slab)           ? kWeightsLdsBySlab
-                                                             : kWeightsL2;
-    static constexpr int bytes = halo(TH) + (WM == kWeightsLds         ? wbytes
-                                             : WM == kWeightsLdsByRow  ? 2 * rslab
-                                             : WM == kWeightsLdsBySlab ? 2 * slab
-                                                                       : 0);
+    // slab state (fragments, slab and halo rows in flight) within two waves'
+    // registers (from the compiled kernels' register counts)
+    static constexpr bool regs8 = NT * (F + 3) * (C / 32) <= 40;
+    static constexpr int pick() {
+        if (ring(8) + wbytes <= kLimit) return 8 * 16 + kWeightsLds;
+        if (regs8 && strm(8) + 2 * rslab <= kLimit) return 8 * 16 + kWeightsLdsByRow + kHaloStream;
+        if (regs8 && strm(8) + 2 * slab <= kLimit) return 8 * 16 + kWeightsLdsBySlab + kHaloStream;
+        if (ring(4) + wbytes <= kLimit) return 4 * 16 + kWeightsLds;
+        if (ring(4) + 2 * rslab <= kLimit) return 4 * 16 + kWeightsLdsByRow;
+        if (strm(4) + 2 * rslab <= kLimit) return 4 * 16 + kWeightsLdsByRow + kHaloStream;
+        if (ring(4) + 2 * slab <= kLimit) return 4 * 16 + kWeightsLdsBySlab;
+        if (strm(4) + 2 * slab <= kLimit) return 4 * 16 + kWeightsLdsBySlab + kHaloStream;
+        return 4 * 16 + kWeightsL2;
+    }
+    static constexpr int TH = pick() / 16, WM = pick() % 16;
+    static constexpr int halo = WM & kHaloStream ? strm(TH) : ring(TH);
+    static constexpr int bytes = halo + ((WM & 3) == kWeightsLds         ? wbytes
+                                         : (WM & 3) == kWeightsLdsByRow  ? 2 * rslab
+                                         : (WM & 3) == kWeightsLdsBySlab ? 2 * slab
+                                                                         : 0);
     static constexpr int threads = 64 * TH;
 };
 
 // Rows hy0 .. hy0+ROWS-1 of a tile's input halo: chunk k = (pixel p = k / CH,
-// channel chunk q = k % CH).  LDS holds the halo as a ring of HH pixel rows:
-// halo row hy of the tile whose first output row is y0 lives in ring slot
-// (y0 + hy) % HH, so the next tile down the same strip finds its first R-1
-// rows in place.
-template <int C, int HW, int HH, int NTHR, int ROWS>
+// channel chunk q = k % CH).  LDS holds halo rows in a ring of NSLOT slots:
+// halo row hy of a tile lives in slot (base + hy) % NSLOT.  With NSLOT =
+// TH+R-1 (the whole halo) and base = the tile's first output row, the next
+// tile down the same strip finds its first R-1 rows in place; with NSLOT =
+// TH+1 and base 0 the rows stream through a window (slab modes).
+template <int C, int HW, int NSLOT, int NTHR, int ROWS>
 struct HaloRows {
     static constexpr int CH = C / 8, KC = C / 32, HW4 = (HW + 3) / 4;
-    static constexpr int ROWB = 4 * HW4 * kRec, PLANE = HH * ROWB;
+    static constexpr int ROWB = 4 * HW4 * kRec, PLANE = NSLOT * ROWB;
     static constexpr int NCHUNK = ROWS * HW * CH, ITERS = (NCHUNK + NTHR - 1) / NTHR;
     static_assert(ITERS <= 32, "one mask bit per chunk");
     // Every load of a thread is issued before any is used.  Chunks outside the
@@ -330,7 +347,7 @@ struct HaloRows {
         for (int it = 0; it < ITERS; ++it) {
             const int k = threadIdx.x + it * NTHR;
             const int p = k / CH, q = k - p * CH;
-            const int slot = (y0 + hy0 + p / HW) % HH, hx = p % HW;
+            const int slot = (y0 + hy0 + p / HW) % NSLOT, hx = p % HW;
             const int pos = (hx & 3) * HW4 + (hx >> 2);
             if (k < NCHUNK)
                 *reinterpret_cast<u32x4 *>(halo + (q >> 2) * PLANE + slot * ROWB + pos * kRec +
@@ -349,32 +366,39 @@ struct HaloRows {
 // TH output rows (= waves) per workgroup; WM: weight placement (WeightMode).
 template <int C, int NT, int R, int S, int TH, int WM>
 __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, int tiles_per_wg) {
-    constexpr bool WL = WM == kWeightsLds, WSLAB = WM == kWeightsLdsBySlab || WM == kWeightsLdsByRow;
-    constexpr int NKC = WM == kWeightsLdsBySlab ? 1 : C / 32;  // c-blocks per pass (and per slab)
+    constexpr int WP = WM & 3;  // weight placement
+    constexpr bool WL = WP == kWeightsLds, WSLAB = WP == kWeightsLdsBySlab || WP == kWeightsLdsByRow;
+    constexpr bool STREAM = (WM & kHaloStream) != 0;
+    constexpr int NKC = WP == kWeightsLdsBySlab ? 1 : C / 32;  // c-blocks per pass (and per slab)
     constexpr int CH = C / 8, KC = C / 32;
     constexpr int HW = kLdsTW + S - 1, HH = TH + R - 1;
+    // A streamed halo passes through TH+1 row slots: filter row r reads rows
+    // r .. r+TH-1, and row r+TH loads into the slot row r-1 has freed.
+    // Otherwise the whole halo is kept as a ring shared with the next tile
+    // down the strip.
+    constexpr int NSLOT = STREAM ? TH + 1 : HH;
     constexpr int NTHR = TH * 64;
-    typedef HaloRows<C, HW, HH, NTHR, HH> Full;
-    typedef HaloRows<C, HW, HH, NTHR, TH> Next;
+    typedef HaloRows<C, HW, NSLOT, NTHR, HH> Full;
+    typedef HaloRows<C, HW, NSLOT, NTHR, TH> Next;
+    typedef HaloRows<C, HW, NSLOT, NTHR, 1> One;
+    // ring slab modes: ring row i is free once filter row i is done; rows
+    // i < R-1 are refilled during filter row i+1, the rest after the tile
+    constexpr int PROG = R - 1 < TH ? R - 1 : TH;
+    constexpr int ENDR = TH - PROG;
+    typedef HaloRows<C, HW, NSLOT, NTHR, (ENDR > 0 ? ENDR : 1)> EndRows;
     constexpr int HW4 = Full::HW4, ROWB = Full::ROWB, PLANE = Full::PLANE;
     constexpr int TAPB = 16 * NT * kRec;  // one (tap, c-block) of the workgroup's weights
     constexpr int SLAB_BYTES = S * NKC * TAPB;    // one slab of weights
     constexpr int WCHUNK = 16 * NT * R * S * CH;  // this workgroup's weight chunks
     constexpr int SCHUNK = 16 * NT * S * NKC * 4; // ... of one slab
-    // The next tile's TH new halo rows replace ring rows this tile has
-    // finished with.  With all weights in LDS they are prefetched into
-    // registers while the tile computes and stored after it.  In slab mode,
-    // whose passes end in barriers, ring row i is free once filter row i is
-    // done: rows i < R-1 are loaded during filter row i and stored at the
-    // start of filter row i+1 (a few registers at a time), the rest during
-    // the last filter row and stored after it.  With weights from L2 (each
-    // weight load would wait behind a prefetch: loads complete in order) the
-    // rows load after the tile.
-    constexpr bool PREFETCH = WM == kWeightsLds;
-    constexpr int PROG = R - 1 < TH ? R - 1 : TH;  // slab mode: ring rows refilled during the tile
-    constexpr int ENDR = TH - PROG;                // ... and at its end
-    typedef HaloRows<C, HW, HH, NTHR, 1> One;
-    typedef HaloRows<C, HW, HH, NTHR, (ENDR > 0 ? ENDR : 1)> EndRows;
+    // Ring modes: the next tile's TH new halo rows replace rows this tile has
+    // finished with; with all weights in LDS they are prefetched into
+    // registers while the tile computes and stored after it; with weights
+    // from L2 (each weight load would wait behind a prefetch: loads complete
+    // in order) they load after the tile.  Slab modes: each filter row loads
+    // the halo row the next one needs, and the last filter row prefetches
+    // the next tile's first TH rows.
+    constexpr bool PREFETCH = WL;
     constexpr int BD = WM == kWeightsL2 ? 2 : 1;  // weight fragments are loaded BD steps ahead
     // weights first (offset 0), then the halo planes
     extern __shared__ __align__(16) unsigned char lds[];
@@ -439,10 +463,17 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
     {
         int b, y0, x0;
         tile_origin(t_begin, b, y0, x0);
-        u32x4 v[Full::ITERS];
-        uint32_t vo;
-        Full::load(a, b, y0, x0, 0, v, vo);
-        Full::store(halo, y0, 0, v, vo);
+        if constexpr (STREAM) {
+            u32x4 v[Next::ITERS];
+            uint32_t vo;
+            Next::load(a, b, y0, x0, 0, v, vo);
+            Next::store(halo, 0, 0, v, vo);
+        } else {
+            u32x4 v[Full::ITERS];
+            uint32_t vo;
+            Full::load(a, b, y0, x0, 0, v, vo);
+            Full::store(halo, y0, 0, v, vo);
+        }
     }
     if constexpr (WL) {
         // all weights of output channels n_blk .. n_blk + 16*NT, staged once:
@@ -494,7 +525,7 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
     // of every workgroup storing at once at its tile end while the matrix
     // cores idle.  (With weights read from L2, each weight load would wait
     // behind the stores: loads and stores share one in-order counter.)
-    constexpr bool DEFER = UNROLLED && WM != kWeightsL2 && TH == 4 && NZ <= 10 && S <= 7;
+    constexpr bool DEFER = UNROLLED && WP != kWeightsL2 && TH == 4 && NZ <= 10 && S <= 5;
     constexpr int NQ = kMT * NT;              // 16-byte stores per lane and tile
     constexpr int ZS = NZ < 4 ? NZ : 4;        // passes they are spread over
     constexpr int QPZ = (NQ + ZS - 1) / ZS;    // ... per pass
@@ -554,7 +585,7 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
         // fragments BD steps ahead.  mid() runs halfway.
         auto pass = [&](int z, auto &&mid) {
             const int r = z * NKC / KC, kc0 = z * NKC - r * KC;
-            const unsigned char *arow = halo + ((y0 + wave + r) % HH) * ROWB;
+            const unsigned char *arow = halo + ((STREAM ? wave + r : y0 + wave + r) % NSLOT) * ROWB;
             u32x4 Af[NKC][kMT + S - 1], Bq[NS][NT];
             auto ld_b = [&](int k) {
                 const int kk = k / S, s = k - kk * S, kc = kc0 + kk;
@@ -606,36 +637,58 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
             }
         };
         auto nothing = [] {};
-        u32x4 pv[One::ITERS], ev[EndRows::ITERS];  // slab mode: refill rows in flight
+        u32x4 pv[One::ITERS], ev[EndRows::ITERS];  // slab modes: halo rows in flight
         uint32_t po = 0, eo = 0;
         if constexpr (WSLAB) {
             // the next slab (slab 0 of the next tile after the last) loads
             // from L2 while this one computes and is stored halfway through
             // it; the barrier after each slab keeps the two buffers' readers
             // and writer apart
-            auto slab = [&](int z) {
+            // LAST: a pass of the last filter row (which prefetches the next
+            // tile's first TH rows; a compile-time flag keeps those registers
+            // out of the other passes)
+            auto slab = [&](int z, auto last) {
                 const bool nxt = z + 1 < NZ || more;
                 const int r = z * NKC / KC;
-                if (z * NKC - r * KC == 0 && down) {  // the first pass of filter row r
+                const bool first = z * NKC - r * KC == 0;  // the first pass of filter row r
+                bool row_in = false;
+                if constexpr (STREAM) {
+                    row_in = first && r + TH < HH;  // this tile's halo row r+TH loads now
+                    if (row_in) One::load(a, b, y0, x0, r + TH, pv, po);
+                    if constexpr (decltype(last)::value) {
+                        if (first && more) {  // the next tile's first TH rows
+                            int b1, y1, x1;
+                            tile_origin(t + 1, b1, y1, x1);
+                            Next::load(a, b1, y1, x1, 0, nh, nho);
+                        }
+                    }
+                } else if (first && down) {  // ring: refill the rows filter row r-1 freed
                     if (r >= 1 && r - 1 < PROG) One::store(halo, y0 + TH, R - 1 + (r - 1), pv, po);
                     if (r < PROG) One::load(a, b, y0 + TH, x0, R - 1 + r, pv, po);
-                    if (ENDR > 0 && r == R - 1) EndRows::load(a, b, y0 + TH, x0, R - 1 + PROG, ev, eo);
+                    if constexpr (ENDR > 0 && decltype(last)::value)
+                        EndRows::load(a, b, y0 + TH, x0, R - 1 + PROG, ev, eo);
                 }
                 u32x4 v[SITERS];
                 if (nxt) wslab_load(z + 1 < NZ ? z + 1 : 0, v);
                 pass(z, [&] {
+                    // row r+TH goes to the slot of row r-1, which no wave reads
+                    // in filter row r (they read rows r .. r+TH-1)
+                    if (row_in) One::store(halo, 0, r + TH, pv, po);
                     if (nxt) wslab_store(wb ^ 1, v);
                 });
                 if (z + 1 < NZ) __syncthreads();
                 wb ^= 1;
             };
+            constexpr int ZPR = KC / NKC;  // passes per filter row
             if constexpr (DEFER) {  // the deferred-store slots need compile-time pass indices
 #pragma unroll
-                for (int z = 0; z < NZ; ++z) slab(z);
+                for (int z = 0; z < NZ - ZPR; ++z) slab(z, std::false_type{});
             } else {  // two waves per SIMD: keep the code (and its registers) to one pass
 #pragma unroll 1
-                for (int z = 0; z < NZ; ++z) slab(z);
+                for (int z = 0; z < NZ - ZPR; ++z) slab(z, std::false_type{});
             }
+#pragma unroll
+            for (int z = NZ - ZPR; z < NZ; ++z) slab(z, std::true_type{});
         } else if constexpr (R <= 7) {  // small filters: the whole walk unrolled (no loop-carried accumulator copies)
 #pragma unroll
             for (int z = 0; z < NZ; ++z) pass(z, nothing);
@@ -663,7 +716,9 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
         }
         if (more) {
             __syncthreads();  // every wave is done with this tile's halo rows
-            if (down) {
+            if constexpr (STREAM) {
+                Next::store(halo, 0, 0, nh, nho);
+            } else if (down) {
                 if constexpr (WSLAB) {
                     if constexpr (ENDR > 0) EndRows::store(halo, y0 + TH, R - 1 + PROG, ev, eo);
                 } else {
