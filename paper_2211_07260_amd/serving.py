@@ -71,9 +71,10 @@ def make_payload(r, device):
         w = torch.rand(r.f, r.f, generator=g, device=device)
         out = torch.empty(r.side, r.side, device=device)
     else:
-        # drawn in BF16 directly: one generator kernel per tensor, no conversion pass
-        img = torch.randn(1, r.side, r.side, r.c, generator=g, device=device, dtype=torch.bfloat16)
-        w = torch.randn(r.c, r.f, r.f, r.c, generator=g, device=device, dtype=torch.bfloat16)
+        # uniform [0, 1) drawn in BF16 directly: one generator kernel per
+        # tensor, no conversion pass (a normal draw costs several times more)
+        img = torch.rand(1, r.side, r.side, r.c, generator=g, device=device, dtype=torch.bfloat16)
+        w = torch.rand(r.c, r.f, r.f, r.c, generator=g, device=device, dtype=torch.bfloat16)
         out = torch.empty(1, r.side, r.side, r.c, device=device)
     return img, w, out
 
