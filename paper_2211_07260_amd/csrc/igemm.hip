@@ -738,75 +738,93 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
     }
 }
 
-constexpr int kValuP = 8, kValuWaves = 4;  // pixels per wave, waves per workgroup
+// FP32 implicit GEMM on the vector ALUs (the comparison path).  A workgroup
+// computes 64 consecutive output pixels of one output row x 64 output
+// channels; thread (tm, tn) holds a 4 x 4 register tile (pixels 4*tm ..,
+// channels 4*tn ..).  The reduction runs over steps (r, s, 16-channel chunk):
+// a step's A (16 channels x 64 pixels, from NHWC input) and B (16 channels x
+// 64 output channels, from KRSC weights) are staged in LDS channel-major and
+// double-buffered, the next step's loads in flight while the current step
+// computes.  Per channel a thread reads 4 pixels and 4 weights (two 16-byte
+// LDS reads, the same addresses across its 16-lane groups) for 16 FMAs
+// v_fmac acc, v_a, v_b.  Each output is one FP32 FMA chain in (r, s, c)
+// order.
+constexpr int kF32M = 64, kF32N = 64, kF32K = 16, kF32Pitch = 68;  // LDS row: 64 values + 4 (bank spread)
 
-// A wave computes kValuP consecutive output pixels of one output row (all
-// 64 output channels of its channel block, one per lane).  The input row
-// pointer and the row check are wave-uniform; in interior tiles every pixel
-// of a filter tap is valid and its 8-channel input chunk is one scalar load
-// at a compile-time offset from the row pointer.
-template <int R, int S, int C>
-__global__ __launch_bounds__(256) void igemm_f32_valu_kernel(IgemmArgs a) {
-    typedef const __attribute__((address_space(4))) float cfloat;
-    const float *__restrict__ wt = static_cast<const float *>(a.w);
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tiles_x = (a.out_w + kValuP - 1) / kValuP;
-    const int tile = blockIdx.x * kValuWaves + wave;
-    const int row = tile / tiles_x;                      // b * out_h + y
-    const int x0 = (tile - row * tiles_x) * kValuP;
-    const int co = blockIdx.y * 64 + lane;
-    if (row >= a.n * a.out_h) return;  // wave-uniform: past the last row
+template <int C>
+__global__ __launch_bounds__(256) void igemm_f32_tiled_kernel(IgemmArgs a, int R, int S) {
+    __shared__ __align__(16) float As[2][kF32K][kF32Pitch];
+    __shared__ __align__(16) float Bs[2][kF32K][kF32Pitch];
+    const int t = threadIdx.x;
+    const int tm = t & 15, tn = t >> 4;
+    const int tiles_x = (a.out_w + kF32M - 1) / kF32M;
+    const int row = blockIdx.x / tiles_x;  // b * out_h + y
+    const int x0 = (blockIdx.x - row * tiles_x) * kF32M;
     const int b = row / a.out_h, y = row - b * a.out_h;
-
-    float acc[kValuP];
+    const int n0 = blockIdx.y * kF32N;
+    const float *in = static_cast<const float *>(a.in);
+    const float *wt = static_cast<const float *>(a.w);
+    // staging: thread t loads 4 channels (quad sq) of pixel / output channel sp
+    const int sp = t >> 2, sq = t & 3;
+    constexpr int CHUNKS = C / kF32K;
+    const int steps = R * S * CHUNKS;
+    // inputs outside the image load a valid address and are zeroed when
+    // stored (zeroing at the load would make the thread wait for it)
+    auto load = [&](int step, float4 &va, float4 &vb, bool &ok) {
+        const int rs = step / CHUNKS, ch = step - rs * CHUNKS;
+        const int r = rs / S, s = rs - r * S;
+        const int c = ch * kF32K + sq * 4;
+        const int yy = y + r - a.ph, xx = x0 + sp + s - a.pw;
+        ok = yy >= 0 && yy < a.h && xx >= 0 && xx < a.wd;
+        va = *reinterpret_cast<const float4 *>(in + (ok ? (((size_t)b * a.h + yy) * a.wd + xx) * C + c : 0));
+        vb = *reinterpret_cast<const float4 *>(wt + (((size_t)(n0 + sp) * R + r) * S + s) * C + c);
+    };
+    auto store = [&](int buf, const float4 &va, const float4 &vb, bool ok) {
+        const float4 z = ok ? va : make_float4(0.f, 0.f, 0.f, 0.f);
+        As[buf][sq * 4 + 0][sp] = z.x;
+        As[buf][sq * 4 + 1][sp] = z.y;
+        As[buf][sq * 4 + 2][sp] = z.z;
+        As[buf][sq * 4 + 3][sp] = z.w;
+        Bs[buf][sq * 4 + 0][sp] = vb.x;
+        Bs[buf][sq * 4 + 1][sp] = vb.y;
+        Bs[buf][sq * 4 + 2][sp] = vb.z;
+        Bs[buf][sq * 4 + 3][sp] = vb.w;
+    };
+    float acc[4][4];
 #pragma unroll
-    for (int p = 0; p < kValuP; ++p) acc[p] = 0.f;
-
-    for (int r = 0; r < R; ++r) {
-        const int yy = y + r - a.ph;
-        if (yy < 0 || yy >= a.h) continue;  // zero padding rows
-        cfloat *rowp = (cfloat *)a.in + ((size_t)b * a.h + yy) * a.wd * C;
-#pragma unroll 1
-        for (int s = 0; s < S; ++s) {
-            const int xs = x0 + s - a.pw;  // input column of pixel 0
-            const float *wrs = wt + (((size_t)co * R + r) * S + s) * C;
-            const bool all = xs >= 0 && xs + kValuP <= a.wd;
-#pragma unroll 1
-            for (int c = 0; c < C; c += 8) {  // one 8-channel chunk: 8 pixels x 8 inputs in SGPRs
-                float wv[8];
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    const float4 v = *reinterpret_cast<const float4 *>(wrs + c + 4 * k);
-                    wv[4 * k] = v.x;
-                    wv[4 * k + 1] = v.y;
-                    wv[4 * k + 2] = v.z;
-                    wv[4 * k + 3] = v.w;
-                }
-                if (all) {
-                    cfloat *px = rowp + (size_t)xs * C + c;
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+    float4 va, vb;
+    bool ok;
+    load(0, va, vb, ok);
+    store(0, va, vb, ok);
+    __syncthreads();
+    for (int step = 0; step < steps; ++step) {
+        const int cur = step & 1;
+        const bool more = step + 1 < steps;
+        if (more) load(step + 1, va, vb, ok);
 #pragma unroll
-                    for (int p = 0; p < kValuP; ++p)
+        for (int k = 0; k < kF32K; ++k) {
+            const float4 av = *reinterpret_cast<const float4 *>(&As[cur][k][tm * 4]);
+            const float4 bv = *reinterpret_cast<const float4 *>(&Bs[cur][k][tn * 4]);
+            const float ai[4] = {av.x, av.y, av.z, av.w}, bj[4] = {bv.x, bv.y, bv.z, bv.w};
 #pragma unroll
-                        for (int k = 0; k < 8; ++k) acc[p] = __builtin_fmaf(px[p * C + k], wv[k], acc[p]);
-                } else {
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
-                    for (int p = 0; p < kValuP; ++p) {
-                        const int xx = xs + p;
-                        if (xx >= 0 && xx < a.wd) {
-                            cfloat *px = rowp + (size_t)xx * C + c;
-#pragma unroll
-                            for (int k = 0; k < 8; ++k) acc[p] = __builtin_fmaf(px[k], wv[k], acc[p]);
-                        }
-                    }
-                }
-            }
+                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_fmaf(ai[i], bj[j], acc[i][j]);
         }
+        // the other buffer was last read in the previous step, before its barrier
+        if (more) store(cur ^ 1, va, vb, ok);
+        __syncthreads();
     }
-    float *dst = a.out + (size_t)row * a.out_w * a.c_out + co;
 #pragma unroll
-    for (int p = 0; p < kValuP; ++p)
-        if (x0 + p < a.out_w) dst[(size_t)(x0 + p) * a.c_out] = acc[p];
+    for (int i = 0; i < 4; ++i) {
+        const int x = x0 + 4 * tm + i;
+        if (x < a.out_w)
+            *reinterpret_cast<float4 *>(a.out + ((size_t)row * a.out_w + x) * a.c_out + n0 + 4 * tn) =
+                make_float4(acc[i][0], acc[i][1], acc[i][2], acc[i][3]);
+    }
 }
 
 namespace {
@@ -844,21 +862,10 @@ const void *mfma_kernel_for(int f, int c, int c_out, bool *generic = nullptr) {
     return fn ? fn : mfma_any_for(c, nt);
 }
 
-template <int R, int S>
-const void *pick_valu(int c) {
-    if (c == 64) return (const void *)&igemm_f32_valu_kernel<R, S, 64>;
-    if (c == 32) return (const void *)&igemm_f32_valu_kernel<R, S, 32>;
+const void *valu_kernel_for(int c) {
+    if (c == 64) return (const void *)&igemm_f32_tiled_kernel<64>;
+    if (c == 32) return (const void *)&igemm_f32_tiled_kernel<32>;
     return nullptr;
-}
-
-const void *valu_kernel_for(int f, int c) {
-    switch (f) {
-        case 1: return pick_valu<1, 1>(c);
-        case 3: return pick_valu<3, 3>(c);
-        case 5: return pick_valu<5, 5>(c);
-        case 7: return pick_valu<7, 7>(c);
-        default: return nullptr;
-    }
 }
 
 struct LdsEntry {
@@ -914,9 +921,8 @@ int validate_igemm(const gt_problem &p, const gt_conv_config &) {
             return set_error(GT_E_UNSUPPORTED, "igemm bf16: c_in %d not instantiated (32 or 64)", p.c_in);
     } else {
         if (p.c_out % 64 != 0) return set_error(GT_E_UNSUPPORTED, "igemm f32: c_out must be a multiple of 64");
-        if (!valu_kernel_for(p.filt_h, p.c_in))
-            return set_error(GT_E_UNSUPPORTED, "igemm f32: c_in %d / filter %d not instantiated (c_in 32 or 64; "
-                             "filter 1, 3, 5, 7)", p.c_in, p.filt_h);
+        if (!valu_kernel_for(p.c_in))
+            return set_error(GT_E_UNSUPPORTED, "igemm f32: c_in %d not instantiated (32 or 64)", p.c_in);
     }
     return GT_OK;
 }
@@ -984,9 +990,13 @@ int launch_igemm(const gt_problem &p, const gt_conv_config &, const void *in, co
             GT_HIP_CHECK(hipLaunchKernel(fn, grid, dim3(256), args, 0, s));
         }
     } else {
-        const int64_t tiles = (int64_t)p.n * p.out_h * ((p.out_w + kValuP - 1) / kValuP);
-        dim3 grid((unsigned)((tiles + kValuWaves - 1) / kValuWaves), (unsigned)(p.c_out / 64));
-        GT_HIP_CHECK(hipLaunchKernel(valu_kernel_for(p.filt_h, p.c_in), grid, dim3(256), args, 0, s));
+        if ((uintptr_t)out & 15) return set_error(GT_E_INVAL, "igemm f32: output must be 16-byte aligned");
+        const int64_t tiles = (int64_t)p.n * p.out_h * ((p.out_w + kF32M - 1) / kF32M);
+        if (tiles >= ((int64_t)1 << 31)) return set_error(GT_E_INVAL, "igemm f32: too many tiles");
+        int R = p.filt_h, S = p.filt_w;
+        void *fargs[] = {&a, &R, &S};
+        dim3 grid((unsigned)tiles, (unsigned)(p.c_out / kF32N));
+        GT_HIP_CHECK(hipLaunchKernel(valu_kernel_for(p.c_in), grid, dim3(256), fargs, 0, s));
     }
     return GT_OK;
 }
