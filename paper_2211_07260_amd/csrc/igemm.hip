@@ -17,10 +17,9 @@
 //   fragments loaded while the current step's MFMAs issue, zero padding as a
 //   masked load) serves the shapes the LDS kernel does not cover.
 //
-// * FP32 on the vector ALUs, the comparison path.  Lanes are output channels
-//   (64 per wave) and a wave owns P pixels, so an input value is the same for
-//   the whole wave: it is read with scalar loads into SGPRs and each FMA is
-//   v_fmac acc, s_x, v_w with the weights in VGPRs (read through L1/L2).
+// * FP32 on the vector ALUs, the comparison path: a register-tiled implicit
+//   GEMM (each thread 4 pixels x 4 output channels) over LDS-staged,
+//   channel-major slices of the input and the weights.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
