@@ -394,7 +394,9 @@ class Batch:
     """A packed batch of single-channel convolutions sharing one filter size
     and config.  convs: list of (d_in, d_filt, d_out, out_h, out_w, f) with
     torch device tensors.  The descriptor blob lives in a device tensor owned
-    by this object."""
+    by this object; its upload is queued on the stream current at
+    construction, so run() on that stream, or order the other stream after it
+    (e.g. a synchronize) before the first run."""
 
     def __init__(self, convs, cfg):
         import torch
