@@ -86,6 +86,24 @@ def igemm_extras(gt, torch, dev, steps=20, energy=True):
     return res
 
 
+def synthetic_loads(gt, torch, dev):
+    """Rate and median socket power of the library's synthetic full loads
+    (FP32 FMA, BF16 MFMA, HBM copy) at the default clock: the loads a
+    per-GPU power-model calibration fits to."""
+    buf = torch.empty(1 << 26, dtype=torch.float32, device=dev)
+    res = {}
+    for kind, name, unit in ((gt.LOAD_FP32_FMA, "fp32_fma", "GFLOP/s"), (gt.LOAD_BF16_MFMA, "bf16_mfma", "GFLOP/s"),
+                             (gt.LOAD_COPY, "copy", "GB/s")):
+        try:
+            m = gt.measure_load(kind, buf, window_s=1.0, discard_s=0.3)
+            res[name] = {"rate": round(m["gflops"], 1), "unit": unit, "p_median_w": m["p_median_w"],
+                         "sclk_mhz": round(m["sclk_act_mhz"], 1)}
+        except gt.GreentuneError as e:
+            res[name] = {"error": str(e)}
+    del buf
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,6 +194,12 @@ def main():
             energy["efficiency_gain_energy_vs_time"] = (energy["energy_tuned"]["gflops_per_w"]
                                                         / energy["time_tuned"]["gflops_per_w"])
 
+    loads = None
+    if not args.no_energy:
+        loads = synthetic_loads(gt, torch, dev)
+        print("bench: synthetic loads " + ", ".join("%s %.0f W" % (k, v.get("p_median_w", float("nan")))
+                                                     for k, v in loads.items()), file=sys.stderr, flush=True)
+
     extras = None
     if not args.no_extras:
         extras = igemm_extras(gt, torch, dev, energy=not args.no_energy)
@@ -217,6 +241,7 @@ def main():
                    "parallelism": "single GPU"},
         "gflops_per_w": (energy or {}).get("time_tuned", {}).get("gflops_per_w"),
         "energy": energy,
+        "synthetic_loads": loads,
         "multichannel": extras,
         "serving": serving_rep,
         "wall_s_timed": round(t_wall, 4),

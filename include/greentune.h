@@ -309,6 +309,24 @@ int gt_ffg_centrality(const gt_conv_config *cfgs, const double *fitness, size_t 
                       const double *p_values, size_t n_p, double *pagerank, int32_t *is_minimum,
                       double *proportion);
 
+/* ---- synthetic full loads (per-GPU power calibration) ---- */
+
+#define GT_LOAD_FP32_FMA   0  /* FP32 FMA chains, the convolution's instruction form, all CUs */
+#define GT_LOAD_BF16_MFMA  1  /* BF16 16x16x32 MFMA chains, two waves per SIMD */
+#define GT_LOAD_COPY       2  /* device copy through HBM */
+
+/* Measure time and energy of a synthetic kernel that fully loads one unit of
+ * the GPU, at a clock, with the same window, sampler and statistics as
+ * measure_time_energy.  Such readings calibrate the power model once per GPU
+ * and serve every kernel tuned on it (the paper's procedure, section V.D).
+ * d_buf: caller-owned device scratch of `bytes` (overwritten): >= 4 MiB
+ * covers every kind.  rec->gflops holds the load's rate: GFLOP/s for the
+ * FMA and MFMA loads, GB/s of read + written bytes for the copy.
+ * Errors: as measure_time_energy; GT_E_INVAL for an unknown kind or a
+ * small buffer. */
+int measure_load(int32_t kind, gt_clock clock, const gt_measure_opts *opts, void *d_buf, size_t bytes,
+                 void *hip_stream, gt_measurement *rec);
+
 /* ---- roofline probes ---- */
 
 /* Measure the achievable FP32 vector FMA rate (FMA with one SGPR operand, the

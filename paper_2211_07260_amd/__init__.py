@@ -127,6 +127,7 @@ def _load():
         "tune_space_enumerate": ([P(Problem), P(SpaceDesc), P(ConvConfig), c_size, P(c_size)], c_int),
         "measure_time_energy": ([P(Problem), P(ConvConfig), Clock, P(MeasureOpts), vp, vp, vp, vp,
                                  P(Measurement)], c_int),
+        "measure_load": ([ctypes.c_int32, Clock, P(MeasureOpts), vp, c_size, vp, P(Measurement)], c_int),
         "fit_power_model": ([P(c_double), P(c_double), P(c_double), c_size, c_double, P(PowerModel)], c_int),
         "gt_power_model_eval": ([P(PowerModel), c_double], c_double),
         "gt_power_model_throttle_clock": ([P(PowerModel)], c_double),
@@ -166,7 +167,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("gt_init", "gt_shutdown", "gt_last_error", "gt_version", "conv2d_run",
-            "tune_space_enumerate", "measure_time_energy", "fit_power_model", "gt_power_model_eval", "gt_power_model_throttle_clock",
+            "tune_space_enumerate", "measure_time_energy", "measure_load", "fit_power_model", "gt_power_model_eval", "gt_power_model_throttle_clock",
             "gt_power_model_band", "gt_energy_from_samples", "gt_select", "gt_problem_flops",
             "gt_conv_lds_bytes", "gt_sensor_read", "gt_settable_clocks", "gt_dvfs_state",
             "gt_fake_sensor_model", "gt_roofline_probe", "gt_mfma_probe", "gt_batch_pack", "conv2d_run_batched",
@@ -274,6 +275,21 @@ def measure_time_energy(problem, cfg, inp, filt, out, clk=None, window_s=1.0, di
     _check(_lib.measure_time_energy(ctypes.byref(problem), ctypes.byref(as_config(cfg)), clk or clock(),
                                     ctypes.byref(o), _ptr(inp), _ptr(filt), _ptr(out), _stream(stream),
                                     ctypes.byref(m)))
+    return m.as_dict()
+
+
+LOAD_FP32_FMA, LOAD_BF16_MFMA, LOAD_COPY = 0, 1, 2
+
+
+def measure_load(kind, buf, clk=None, window_s=1.0, discard_s=0.3, sample_period_ms=1.0, min_launches=10,
+                 warmup_launches=3, stream=None):
+    """Time and energy of a synthetic full-load kernel (LOAD_*) at a clock;
+    buf: device tensor of >= 4 MiB (overwritten).  'gflops' is GB/s for the
+    copy load."""
+    o = MeasureOpts(window_s, discard_s, sample_period_ms, min_launches, warmup_launches)
+    m = Measurement()
+    _check(_lib.measure_load(int(kind), clk or clock(), ctypes.byref(o), _ptr(buf), buf.numel() * buf.element_size(),
+                             _stream(stream), ctypes.byref(m)))
     return m.as_dict()
 
 

@@ -51,6 +51,9 @@ int validate_igemm(const gt_problem &p, const gt_conv_config &c);
 int launch_igemm(const gt_problem &p, const gt_conv_config &c, const void *in, const void *w,
                  void *out, hipStream_t s);
 int validate_problem_config(const gt_problem &p, const gt_conv_config &c);
+// synthetic full loads (roofline_probe.hip): work per launch, and one launch
+int load_work(int kind, size_t bytes, double *work);
+int launch_load(int kind, void *buf, size_t bytes, hipStream_t s);
 int launch_problem(const gt_problem &p, const gt_conv_config &c, const void *in, const void *w,
                    void *out, hipStream_t s);
 

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <functional>
 #include <thread>
 
 #include "gt_internal.hpp"
@@ -28,35 +29,24 @@ struct EventPair {
 
 }  // namespace
 
-extern "C" int measure_time_energy(const gt_problem *problem, const gt_conv_config *config,
-                                   gt_clock clock, const gt_measure_opts *opts, const void *d_in,
-                                   const void *d_filt, void *d_out, void *hip_stream,
-                                   gt_measurement *rec) {
-    clear_error();
-    if (!problem || !config || !d_in || !d_filt || !d_out || !rec)
-        return set_error(GT_E_INVAL, "measure_time_energy: null argument");
-    if (!state().inited) return set_error(GT_E_STATE, "measure_time_energy: call gt_init first");
-    if (state().flags & GT_INIT_HOST_ONLY)
-        return set_error(GT_E_STATE, "measure_time_energy: library initialised host-only");
-    gt_measure_opts o = opts ? *opts : gt_measure_opts{0, -1, 0, 0, -1};
+namespace gt {
+
+// The measurement window shared by measure_time_energy and measure_load:
+// warm-up launches, an estimate of the launch time, then launches back to
+// back for the window while the sampler records the sensor.
+int measure_window(const std::function<int(hipStream_t)> &launch, double flops_per_launch, gt_measure_opts o,
+                   hipStream_t s, gt_measurement *rec) {
     if (!(o.window_s > 0)) o.window_s = 1.0;
     if (o.discard_s < 0) o.discard_s = 0.3;
     if (!(o.sample_period_ms > 0)) o.sample_period_ms = 1.0;
     if (o.min_launches <= 0) o.min_launches = 10;
     if (o.warmup_launches < 0) o.warmup_launches = 3;
     if (o.discard_s >= o.window_s)
-        return set_error(GT_E_INVAL, "measure_time_energy: discard %.3f s >= window %.3f s",
-                         o.discard_s, o.window_s);
-    int rc = validate_problem_config(*problem, *config);
+        return set_error(GT_E_INVAL, "measure: discard %.3f s >= window %.3f s", o.discard_s, o.window_s);
+    int rc = sensor_open();
     if (rc) return rc;
-    rc = dvfs_apply(clock);
-    if (rc) return rc;
-    rc = sensor_open();
-    if (rc) return rc;
-    hipStream_t s = (hipStream_t)hip_stream;
-
     for (int k = 0; k < o.warmup_launches; ++k) {
-        rc = launch_problem(*problem, *config, d_in, d_filt, d_out, s);
+        rc = launch(s);
         if (rc) return rc;
     }
     EventPair est, win;
@@ -66,7 +56,7 @@ extern "C" int measure_time_energy(const gt_problem *problem, const gt_conv_conf
     GT_HIP_CHECK(hipEventCreate(&win.b));
     GT_HIP_CHECK(hipEventRecord(est.a, s));
     for (int k = 0; k < 3; ++k) {
-        rc = launch_problem(*problem, *config, d_in, d_filt, d_out, s);
+        rc = launch(s);
         if (rc) return rc;
     }
     GT_HIP_CHECK(hipEventRecord(est.b, s));
@@ -96,7 +86,7 @@ extern "C" int measure_time_energy(const gt_problem *problem, const gt_conv_conf
     hipError_t herr = hipEventRecord(win.a, s);
     int64_t launched = 0;
     for (; launched < n && herr == hipSuccess; ++launched) {
-        rc = launch_problem(*problem, *config, d_in, d_filt, d_out, s);
+        rc = launch(s);
         if (rc) break;
     }
     if (herr == hipSuccess && rc == GT_OK) herr = hipEventRecord(win.b, s);
@@ -124,8 +114,8 @@ extern "C" int measure_time_energy(const gt_problem *problem, const gt_conv_conf
         }
     }
     if (kept_p.empty())
-        return set_error(GT_E_SENSOR, "measure_time_energy: no power sample in the kept window "
-                                      "(%zu samples, sensor errors %d)", samples.size(), sensor_err.load());
+        return set_error(GT_E_SENSOR, "measure: no power sample in the kept window (%zu samples, sensor errors %d)",
+                         samples.size(), sensor_err.load());
     gt_measurement &m = *rec;
     m = gt_measurement();
     m.launches = launched;
@@ -154,9 +144,8 @@ extern "C" int measure_time_energy(const gt_problem *problem, const gt_conv_conf
         if (ua && ub && ub->energy_t_s > ua->energy_t_s)
             m.e_run_counter_j = (ub->energy_j - ua->energy_j) / (ub->energy_t_s - ua->energy_t_s) * m.t_run_s;
     }
-    const double flops = gt_problem_flops(problem);
-    m.gflops = flops / m.t_run_s * 1e-9;
-    m.gflops_per_w = flops / m.e_run_j * 1e-9;
+    m.gflops = flops_per_launch / m.t_run_s * 1e-9;
+    m.gflops_per_w = flops_per_launch / m.e_run_j * 1e-9;
     m.sclk_req_mhz = dvfs_requested_mhz();
     m.sclk_act_mhz = sclk_n ? sclk_sum / sclk_n : NAN;
     const gt_sensor_sample &tail = samples.back();
@@ -166,4 +155,44 @@ extern "C" int measure_time_energy(const gt_problem *problem, const gt_conv_conf
     m.throttled = (m.sclk_req_mhz > 0 && sclk_n && m.sclk_act_mhz < 0.98 * m.sclk_req_mhz) ? 1 : 0;
     m.flags = ((state().flags & GT_INIT_FAKE_SENSOR) ? 1 : 0) | ((state().flags & GT_INIT_FAKE_DVFS) ? 2 : 0);
     return GT_OK;
+}
+
+}  // namespace gt
+
+extern "C" int measure_time_energy(const gt_problem *problem, const gt_conv_config *config,
+                                   gt_clock clock, const gt_measure_opts *opts, const void *d_in,
+                                   const void *d_filt, void *d_out, void *hip_stream,
+                                   gt_measurement *rec) {
+    clear_error();
+    if (!problem || !config || !d_in || !d_filt || !d_out || !rec)
+        return set_error(GT_E_INVAL, "measure_time_energy: null argument");
+    if (!state().inited) return set_error(GT_E_STATE, "measure_time_energy: call gt_init first");
+    if (state().flags & GT_INIT_HOST_ONLY)
+        return set_error(GT_E_STATE, "measure_time_energy: library initialised host-only");
+    const gt_measure_opts o = opts ? *opts : gt_measure_opts{0, -1, 0, 0, -1};
+    if (o.window_s > 0 && o.discard_s >= o.window_s)
+        return set_error(GT_E_INVAL, "measure_time_energy: discard %.3f s >= window %.3f s", o.discard_s,
+                         o.window_s);
+    int rc = validate_problem_config(*problem, *config);
+    if (rc) return rc;
+    rc = dvfs_apply(clock);
+    if (rc) return rc;
+    return measure_window([&](hipStream_t s) { return launch_problem(*problem, *config, d_in, d_filt, d_out, s); },
+                          gt_problem_flops(problem), o, (hipStream_t)hip_stream, rec);
+}
+
+extern "C" int measure_load(int32_t kind, gt_clock clock, const gt_measure_opts *opts, void *d_buf, size_t bytes,
+                            void *hip_stream, gt_measurement *rec) {
+    clear_error();
+    if (!d_buf || !rec) return set_error(GT_E_INVAL, "measure_load: null argument");
+    if (!state().inited) return set_error(GT_E_STATE, "measure_load: call gt_init first");
+    if (state().flags & GT_INIT_HOST_ONLY) return set_error(GT_E_STATE, "measure_load: library initialised host-only");
+    double work = 0;
+    int rc = load_work(kind, bytes, &work);
+    if (rc) return rc;
+    rc = dvfs_apply(clock);
+    if (rc) return rc;
+    const gt_measure_opts o = opts ? *opts : gt_measure_opts{0, -1, 0, 0, -1};
+    return measure_window([&](hipStream_t s) { return launch_load(kind, d_buf, bytes, s); }, work, o,
+                          (hipStream_t)hip_stream, rec);
 }

@@ -60,6 +60,59 @@ __global__ __launch_bounds__(256) void copy_kernel(const float4 *__restrict__ sr
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) dst[i] = src[i];
 }
 
+// Synthetic full-load kernels for measure_load: work per launch (flops, or
+// bytes moved for the copy) and the launch itself.
+namespace {
+constexpr int kLoadFmaIters = 256, kLoadMfmaIters = 512;
+int load_cus() { return state().dev.cu_count > 0 ? state().dev.cu_count : 256; }
+}  // namespace
+
+int load_work(int kind, size_t bytes, double *work) {
+    const int cus = load_cus();
+    switch (kind) {
+        case GT_LOAD_FP32_FMA: {
+            const int blocks = cus * 8;
+            if ((size_t)(blocks * 256 + 8) * sizeof(float) > bytes)
+                return set_error(GT_E_INVAL, "measure_load: buffer too small for the FMA load");
+            *work = 2.0 * 256.0 * kLoadFmaIters * (double)blocks * 256;
+            return GT_OK;
+        }
+        case GT_LOAD_BF16_MFMA: {
+            const int blocks = cus * 2;
+            if ((size_t)blocks * 256 * sizeof(float) > bytes)
+                return set_error(GT_E_INVAL, "measure_load: buffer too small for the MFMA load");
+            *work = 16384.0 * 16.0 * kLoadMfmaIters * (double)blocks * 4;
+            return GT_OK;
+        }
+        case GT_LOAD_COPY: {
+            const size_t half = (bytes / 2) / 16 * 16;
+            if (half < (1u << 20)) return set_error(GT_E_INVAL, "measure_load: the copy load needs >= 2 MiB");
+            *work = 2.0 * (double)half;
+            return GT_OK;
+        }
+        default:
+            return set_error(GT_E_INVAL, "measure_load: unknown load kind %d", kind);
+    }
+}
+
+int launch_load(int kind, void *buf, size_t bytes, hipStream_t s) {
+    const int cus = load_cus();
+    float *out = static_cast<float *>(buf);
+    if (kind == GT_LOAD_FP32_FMA) {
+        const int blocks = cus * 8;
+        hipLaunchKernelGGL(fma_peak_kernel, dim3(blocks), dim3(256), 0, s, out, out + blocks * 256, kLoadFmaIters);
+    } else if (kind == GT_LOAD_BF16_MFMA) {
+        hipLaunchKernelGGL(mfma_peak_kernel, dim3(cus * 2), dim3(256), 0, s, out, kLoadMfmaIters);
+    } else {
+        const size_t half = (bytes / 2) / 16 * 16;
+        const float4 *src = static_cast<const float4 *>(buf);
+        float4 *dst = reinterpret_cast<float4 *>(static_cast<char *>(buf) + half);
+        hipLaunchKernelGGL(copy_kernel, dim3(cus * 16), dim3(256), 0, s, src, dst, half / 16);
+    }
+    GT_HIP_CHECK(hipGetLastError());
+    return GT_OK;
+}
+
 }  // namespace gt
 
 using namespace gt;

@@ -173,23 +173,17 @@ def fit_clocks(settable, n=5):
     return out
 
 
-def steered_search(measure, configs, settable, p_max, n_fit=5, rel_half=0.1, fit_config=None):
-    """The paper's procedure (section V.D): fit Eq. 2/3 to <= n_fit power
-    readings of one fully-loading config, take the clock minimising P*(f)/f,
-    and measure the candidate configs only at the settable clocks within
-    +-rel_half of it.
-
-    The model is fitted up to the highest clock before throttling, so the
-    first reading is taken at the top clock: if the device throttles there,
-    the remaining readings are spread uniformly below the clock it sustained
-    instead of over the whole range.  Throttled readings are not fitted.
-
-    measure(config, clock_mhz) -> dict with t_run_s, e_run_j, p_median_w,
-    sclk_act_mhz, throttled.  Returns a report dict."""
-    fit_config = fit_config or configs[0]
+def fit_readings(measure_at, settable, p_max, n_fit=5):
+    """<= n_fit power readings of one fully-loading workload and the fit of
+    Eq. 2/3 to them (section V.D).  The model is fitted up to the highest
+    clock before throttling, so the first reading is taken at the top clock:
+    if the device throttles there, the remaining readings are spread uniformly
+    below the clock it sustained instead of over the whole range.  Throttled
+    readings are not fitted.  measure_at(clock_mhz) -> dict with p_median_w,
+    sclk_act_mhz, throttled.  Returns (readings, PowerModel)."""
     s = sorted(settable)
-    top = measure(fit_config, s[-1])
-    fit_pts = [{"clock_mhz": s[-1], **top}]
+    top = measure_at(s[-1])
+    pts = [{"clock_mhz": s[-1], **top}]
     f_hi = s[-1]
     if top.get("throttled"):
         below = [f for f in s if f <= top.get("sclk_act_mhz", s[-1])]
@@ -197,9 +191,42 @@ def steered_search(measure, configs, settable, p_max, n_fit=5, rel_half=0.1, fit
     for f in fit_clocks([f for f in s if f <= f_hi], n_fit - 1 if top.get("throttled") else n_fit):
         if f == s[-1]:
             continue
-        fit_pts.append({"clock_mhz": f, **measure(fit_config, f)})
-    use = [p for p in fit_pts if not p.get("throttled")]
+        pts.append({"clock_mhz": f, **measure_at(f)})
+    use = [p for p in pts if not p.get("throttled")]
     model = gt.fit_power_model([p["clock_mhz"] for p in use], [p["p_median_w"] for p in use], p_max)
+    return pts, model
+
+
+def calibrate(kind, buf, settable, p_max, n_fit=5, window_s=1.0, discard_s=0.3):
+    """Fit the power model once per GPU from <= n_fit readings of a synthetic
+    full-load kernel (gt.LOAD_*), to be reused for every kernel tuned on that
+    GPU (steered_search(..., model=...)): the paper's procedure of calibrating
+    with a load that fully occupies the device.  buf: device scratch (>= 4 MiB)."""
+    def measure_at(f):
+        return gt.measure_load(kind, buf, gt.clock(gt.CLOCK_SCLK_MHZ, int(f)), window_s=window_s,
+                               discard_s=discard_s)
+    pts, model = fit_readings(measure_at, settable, p_max, n_fit)
+    return {"kind": kind, "fit_points": pts, "model": model.as_dict()}
+
+
+def steered_search(measure, configs, settable, p_max, n_fit=5, rel_half=0.1, fit_config=None, model=None):
+    """The paper's procedure (section V.D): fit Eq. 2/3 to <= n_fit power
+    readings of one fully-loading config (fit_readings), take the clock
+    minimising P*(f)/f, and measure the candidate configs only at the
+    settable clocks within +-rel_half of it.  With `model` (a PowerModel or
+    its as_dict(), e.g. from calibrate) no fit readings are taken.
+
+    measure(config, clock_mhz) -> dict with t_run_s, e_run_j, p_median_w,
+    sclk_act_mhz, throttled.  Returns a report dict."""
+    s = sorted(settable)
+    if model is None:
+        fit_config = fit_config or configs[0]
+        fit_pts, model = fit_readings(lambda f: measure(fit_config, f), s, p_max, n_fit)
+    else:
+        fit_pts = []
+        if isinstance(model, dict):
+            model = gt.power_model(model["p_idle"], model["alpha"], model["beta"], model["tau_mhz"], model["p_max"],
+                                   literal=bool(model.get("literal_eq3", 0)))
     f_opt, band = gt.power_model_band(model, s, rel_half)
     rows = []
     for cfg in configs:

@@ -102,3 +102,34 @@ def test_fake_dvfs_tuning_methods(gt):
         assert rep["global_energy_to_solution"]["e_run_j"] == best["e_run_j"]
     finally:
         gt.shutdown()
+
+
+def test_fake_dvfs_calibration_with_synthetic_loads(gt):
+    # the three synthetic full loads run and report their rates; the power
+    # model fitted from <= 5 readings of one of them (fake sensor, exact
+    # model) recovers that model, and steering with it takes no more readings
+    from paper_2211_07260_amd import tuner
+    gt.init(0, gt.INIT_FAKE_SENSOR | gt.INIT_FAKE_DVFS)
+    try:
+        m = gt.power_model(MODEL["p_idle"], MODEL["alpha"], MODEL["beta"], MODEL["tau"], MODEL["p_max"])
+        gt.fake_sensor_model(m, noise_w=0.0)
+        buf = torch.empty(1 << 22, dtype=torch.float32, device=torch.device("cuda:0"))
+        for kind in (gt.LOAD_FP32_FMA, gt.LOAD_BF16_MFMA, gt.LOAD_COPY):
+            r = gt.measure_load(kind, buf, gt.clock(gt.CLOCK_SCLK_MHZ, 1500), window_s=0.1, discard_s=0.02)
+            assert r["gflops"] > 0 and r["launches"] >= 10
+            assert r["p_median_w"] == pytest.approx(gt.power_model_eval(m, 1500), rel=1e-12)
+        settable = gt.settable_clocks(100.0)
+        cal = tuner.calibrate(gt.LOAD_FP32_FMA, buf, settable, MODEL["p_max"], window_s=0.1, discard_s=0.02)
+        assert len(cal["fit_points"]) <= 5
+        assert cal["model"]["rss"] < 1e-6
+        assert cal["model"]["alpha"] == pytest.approx(MODEL["alpha"], rel=1e-4)
+        img, w, out = bufs(side=512)
+        prob = gt.xcorr_problem(512, 512, 17, 17)
+
+        def measure(c, f):
+            return gt.measure_time_energy(prob, c, img, w, out, gt.clock(gt.CLOCK_SCLK_MHZ, int(f)),
+                                          window_s=0.05, discard_s=0.01)
+        rep = tuner.steered_search(measure, [(32, 8, 4, 2, 0, 0)], settable, MODEL["p_max"], model=cal["model"])
+        assert rep["fit_points"] == [] and rep["band_mhz"]
+    finally:
+        gt.shutdown()

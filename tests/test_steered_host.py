@@ -66,3 +66,30 @@ def test_fit_clocks_uniform_and_snapped():
     settable = list(np.arange(500.0, 2400.0 + 1e-9, 25.0))
     fc = tuner.fit_clocks(settable, 5)
     assert fc == [500.0, 975.0, 1450.0, 1925.0, 2400.0]
+
+
+def test_steered_with_calibrated_model_takes_no_fit_readings():
+    # fit once (calibration), then tune with that model: the same band and
+    # clock choice as fitting inside the search, without its readings
+    model = dict(p_idle=250.0, alpha=0.35, beta=1.2e-3, tau=1250.0, p_max=1400.0)
+    cfgs = [(16, 16, 4, 2, 1, 0), (32, 8, 4, 4, 0, 0)]
+    t_at_max = {c: 1.4e-4 * (1 + 0.1 * k) for k, c in enumerate(cfgs)}
+    settable = list(np.arange(500.0, 2400.0 + 1e-9, 10.0))
+    meas = device(model, t_at_max, 2400.0, 0.0, 0)
+    fitted = tuner.steered_search(meas, cfgs, settable, p_max=model["p_max"], n_fit=5)
+    reused = tuner.steered_search(meas, cfgs, settable, p_max=model["p_max"], model=fitted["model"])
+    assert reused["fit_points"] == []
+    assert reused["band_mhz"] == fitted["band_mhz"] and reused["f_opt_mhz"] == fitted["f_opt_mhz"]
+    assert reused["points_measured_total"] == reused["points_measured_band"] == len(cfgs) * len(reused["band_mhz"])
+    assert reused["best"]["clock_mhz"] == fitted["best"]["clock_mhz"]
+
+
+def test_fit_readings_start_at_top_clock_and_skip_throttled():
+    model = dict(p_idle=250.0, alpha=0.45, beta=2e-3, tau=1200.0, p_max=1000.0)  # throttles near the top
+    cfgs = [(16, 16, 4, 2, 1, 0)]
+    meas = device(model, {cfgs[0]: 1.4e-4}, 2400.0, 0.0, 0)
+    settable = list(np.arange(500.0, 2400.0 + 1e-9, 10.0))
+    pts, fit = tuner.fit_readings(lambda f: meas(cfgs[0], f), settable, model["p_max"], n_fit=5)
+    assert pts[0]["clock_mhz"] == 2400.0 and pts[0]["throttled"]
+    assert len(pts) <= 5
+    assert all(p["clock_mhz"] <= pts[0]["sclk_act_mhz"] for p in pts[1:])
