@@ -538,7 +538,7 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
     int sv_xl = 0;  // M-tiles m < sv_xl of this lane are inside the output row
     auto store_q = [&](int q) {
         const int m = q / NT, j = q - m * NT;
-        if (m < sv_xl) *reinterpret_cast<f32x4 *>(sv_dst + (size_t)m * a.c_out + 16 * j) = sv[m][j];
+        if (m < sv_xl) __builtin_nontemporal_store(sv[m][j], reinterpret_cast<f32x4 *>(sv_dst + (size_t)m * a.c_out + 16 * j));
     };
 
     for (int t = t_begin; t < t_end; ++t) {

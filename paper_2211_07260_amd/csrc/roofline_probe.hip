@@ -54,10 +54,20 @@ __global__ __launch_bounds__(256) void mfma_peak_kernel(float *out, int iters) {
     out[blockIdx.x * blockDim.x + threadIdx.x] = t;
 }
 
-__global__ __launch_bounds__(256) void copy_kernel(const float4 *__restrict__ src, float4 *__restrict__ dst,
+typedef float f4v __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void copy_kernel(const float4 *__restrict__ src0, float4 *__restrict__ dst0,
                                                    size_t n4) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) dst[i] = src[i];
+    const f4v *src = (const f4v *)src0;
+    f4v *dst = (f4v *)dst0;
+    const size_t per_trip = (size_t)gridDim.x * 512;
+    for (size_t base = (size_t)blockIdx.x * 512 + threadIdx.x; base < n4; base += per_trip) {
+        f4v v0 = {0.f, 0.f, 0.f, 0.f}, v1 = v0;
+        const bool two = base + 256 < n4;
+        v0 = __builtin_nontemporal_load(&src[base]);
+        if (two) v1 = __builtin_nontemporal_load(&src[base + 256]);
+        __builtin_nontemporal_store(v0, &dst[base]);
+        if (two) __builtin_nontemporal_store(v1, &dst[base + 256]);
+    }
 }
 
 // Synthetic full-load kernels for measure_load: work per launch (flops, or
@@ -107,7 +117,7 @@ int launch_load(int kind, void *buf, size_t bytes, hipStream_t s) {
         const size_t half = (bytes / 2) / 16 * 16;
         const float4 *src = static_cast<const float4 *>(buf);
         float4 *dst = reinterpret_cast<float4 *>(static_cast<char *>(buf) + half);
-        hipLaunchKernelGGL(copy_kernel, dim3(cus * 16), dim3(256), 0, s, src, dst, half / 16);
+        hipLaunchKernelGGL(copy_kernel, dim3(cus * 64), dim3(256), 0, s, src, dst, half / 16);
     }
     GT_HIP_CHECK(hipGetLastError());
     return GT_OK;
@@ -147,10 +157,10 @@ extern "C" int gt_roofline_probe(void *d_buf, size_t bytes, void *hip_stream, do
     const size_t n4 = half / 16;
     const float4 *src = static_cast<const float4 *>(d_buf);
     float4 *dst = reinterpret_cast<float4 *>(static_cast<char *>(d_buf) + half);
-    hipLaunchKernelGGL(copy_kernel, dim3(cus * 16), dim3(256), 0, s, src, dst, n4);
+    hipLaunchKernelGGL(copy_kernel, dim3(cus * 64), dim3(256), 0, s, src, dst, n4);
     GT_HIP_CHECK(hipEventRecord(a, s));
     const int reps = 10;
-    for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(copy_kernel, dim3(cus * 16), dim3(256), 0, s, src, dst, n4);
+    for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(copy_kernel, dim3(cus * 64), dim3(256), 0, s, src, dst, n4);
     GT_HIP_CHECK(hipEventRecord(b, s));
     GT_HIP_CHECK(hipEventSynchronize(b));
     GT_HIP_CHECK(hipEventElapsedTime(&ms, a, b));

@@ -79,6 +79,7 @@ __device__ __forceinline__ void fma_row(float (&acc)[TY][TX], int r, const float
 
 // Store a thread's TY x TX tile at (y, x).  Full tiles of aligned rows use
 // 16-byte stores; otherwise each element is bounds-checked.
+typedef float f4nt __attribute__((ext_vector_type(4)));
 template <int TX, int TY>
 __device__ __forceinline__ void store_tile(const float (&acc)[TY][TX], float *out, int out_h, int out_w,
                                            int y, int x, bool full) {
@@ -89,7 +90,7 @@ __device__ __forceinline__ void store_tile(const float (&acc)[TY][TX], float *ou
                 float4 *dst = reinterpret_cast<float4 *>(out + (size_t)(y + r) * out_w + x);
 #pragma unroll
                 for (int k = 0; k < TX / 4; ++k)
-                    dst[k] = make_float4(acc[r][4 * k], acc[r][4 * k + 1], acc[r][4 * k + 2], acc[r][4 * k + 3]);
+                    __builtin_nontemporal_store(f4nt{acc[r][4 * k], acc[r][4 * k + 1], acc[r][4 * k + 2], acc[r][4 * k + 3]}, (f4nt *)&dst[k]);
             }
             return;
         }
