@@ -197,8 +197,15 @@ def main():
     loads = None
     if not args.no_energy:
         loads = synthetic_loads(gt, torch, dev)
+        try:
+            lo, hi, cur = gt.power_cap_range()
+            loads["power_cap_w"] = {"min": None if lo != lo else lo, "max": None if hi != hi else hi,
+                                    "in_force": None if cur != cur else cur}
+        except gt.GreentuneError as e:
+            loads["power_cap_w"] = {"error": str(e)}
         print("bench: synthetic loads " + ", ".join("%s %.0f W" % (k, v.get("p_median_w", float("nan")))
-                                                     for k, v in loads.items()), file=sys.stderr, flush=True)
+                                                     for k, v in loads.items() if k != "power_cap_w"),
+              file=sys.stderr, flush=True)
 
     extras = None
     if not args.no_extras:

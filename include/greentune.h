@@ -147,7 +147,7 @@ typedef struct {
 /* ---- lifecycle ---- */
 #define GT_INIT_FAKE_SENSOR 1u  /* synthetic power: P*(f) of gt_fake_sensor_model at the set clock */
 #define GT_INIT_FAKE_DVFS   2u  /* clock knob is recorded, hardware untouched */
-#define GT_INIT_ALLOW_DVFS  4u  /* permit real DVFS changes (needs privileges) */
+#define GT_INIT_ALLOW_DVFS  4u  /* permit real DVFS changes through the registered backend */
 #define GT_INIT_HOST_ONLY   8u  /* no HIP calls at all (host arithmetic only) */
 
 /* Select the HIP device, open the power sensor (amd-smi) and DVFS controller.
@@ -252,6 +252,33 @@ int gt_sensor_busy(int busy);
  * at step_mhz spacing; the fake DVFS backend reports 500..2400).
  * GT_E_CAPACITY if cap is too small (*n still written). */
 int gt_settable_clocks(double step_mhz, double *mhz, size_t cap, size_t *n);
+/* DVFS backend: the library changes no device setting itself.  A caller
+ * with the privileges to change the graphics-clock limit or the socket power
+ * cap (the two knobs of sections III.C and V.C) registers functions that do
+ * it; with GT_INIT_ALLOW_DVFS, a measurement's clock argument then calls
+ * apply(user, device_ordinal, kind, value) (kind GT_CLOCK_SCLK_MHZ or
+ * GT_CLOCK_POWER_CAP_W; value in MHz or W; 0 = success) whenever the knob
+ * changes, and gt_shutdown calls restore(user, device_ordinal) (may be
+ * NULL) to return the device to its defaults.  The structure is copied;
+ * NULL unregisters.  GT_E_STATE while a knob set through the backend is
+ * still in force.  Without a backend, DVFS requests fail with GT_E_PERM. */
+typedef struct {
+    int (*apply)(void *user, int32_t device_ordinal, int32_t kind, int32_t value);
+    int (*restore)(void *user, int32_t device_ordinal);
+    void *user;
+} gt_dvfs_backend;
+int gt_dvfs_set_backend(const gt_dvfs_backend *backend);
+
+/* Power-cap range of the device in W (amd-smi: minimum and maximum settable
+ * cap, and the cap in force), the range a power-cap sweep samples (the
+ * comparison of power capping with clock tuning, section V.C).  With
+ * GT_INIT_FAKE_DVFS: 0.5 * P_max .. P_max of the gt_fake_sensor_model model,
+ * and under a fake cap the fake sensor reports the highest clock (0.01 MHz
+ * grid, 500..2400 MHz) whose model power fits within the cap, or 500 MHz.
+ * A field amd-smi reports as 0 is read from the hwmon files power1_cap_min,
+ * power1_cap_max, power1_cap; NaN where neither reports it (GT_E_SENSOR if
+ * none of the three is known). */
+int gt_power_cap_range(double *min_w, double *max_w, double *current_w);
 /* Current DVFS state: 1 if a knob set through the library is active. */
 int gt_dvfs_state(gt_clock *current);
 /* Synthetic power for GT_INIT_FAKE_SENSOR: readings follow the model at the

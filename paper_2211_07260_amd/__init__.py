@@ -56,6 +56,14 @@ class SpaceDesc(ctypes.Structure):
                 ("lds_limit_bytes", ctypes.c_int64)]
 
 
+DVFS_APPLY = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32)
+DVFS_RESTORE = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int32)
+
+
+class DvfsBackend(ctypes.Structure):
+    _fields_ = [("apply", DVFS_APPLY), ("restore", DVFS_RESTORE), ("user", ctypes.c_void_p)]
+
+
 class MeasureOpts(ctypes.Structure):
     _fields_ = [("window_s", ctypes.c_double), ("discard_s", ctypes.c_double),
                 ("sample_period_ms", ctypes.c_double), ("min_launches", ctypes.c_int32),
@@ -141,6 +149,8 @@ def _load():
         "gt_sensor_read": ([P(SensorSample)], c_int),
         "gt_settable_clocks": ([c_double, P(c_double), c_size, P(c_size)], c_int),
         "gt_dvfs_state": ([P(Clock)], c_int),
+        "gt_power_cap_range": ([P(c_double), P(c_double), P(c_double)], c_int),
+        "gt_dvfs_set_backend": ([P(DvfsBackend)], c_int),
         "gt_fake_sensor_model": ([P(PowerModel), c_double, ctypes.c_uint64], c_int),
         "gt_roofline_probe": ([vp, c_size, vp, P(c_double), P(c_double)], c_int),
         "gt_mfma_probe": ([vp, c_size, vp, P(c_double), P(c_double)], c_int),
@@ -169,7 +179,7 @@ _lib = _load()
 EXPORTED = ("gt_init", "gt_shutdown", "gt_last_error", "gt_version", "conv2d_run",
             "tune_space_enumerate", "measure_time_energy", "measure_load", "fit_power_model", "gt_power_model_eval", "gt_power_model_throttle_clock",
             "gt_power_model_band", "gt_energy_from_samples", "gt_select", "gt_problem_flops",
-            "gt_conv_lds_bytes", "gt_sensor_read", "gt_settable_clocks", "gt_dvfs_state",
+            "gt_conv_lds_bytes", "gt_sensor_read", "gt_settable_clocks", "gt_dvfs_state", "gt_power_cap_range", "gt_dvfs_set_backend",
             "gt_fake_sensor_model", "gt_roofline_probe", "gt_mfma_probe", "gt_batch_pack", "conv2d_run_batched",
             "gt_graph_begin", "gt_graph_end", "gt_graph_launch", "gt_graph_destroy", "gt_sampler_start",
             "gt_sampler_stop", "gt_sensor_busy", "gt_ffg_centrality")
@@ -367,6 +377,31 @@ def settable_clocks(step_mhz=25.0):
     arr = (ctypes.c_double * max(n.value, 1))()
     _check(_lib.gt_settable_clocks(step_mhz, arr, n.value, ctypes.byref(n)))
     return [arr[k] for k in range(n.value)]
+
+
+def power_cap_range():
+    """(min, max, current) power cap in W (amd-smi, or the fake backend's)."""
+    lo, hi, cur = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+    _check(_lib.gt_power_cap_range(ctypes.byref(lo), ctypes.byref(hi), ctypes.byref(cur)))
+    return lo.value, hi.value, cur.value
+
+
+_backend_refs = []
+
+
+def set_dvfs_backend(apply, restore=None):
+    """Register the functions that change the device's DVFS knob (the library
+    changes no device setting itself): apply(device_ordinal, kind, value) ->
+    0 on success, restore(device_ordinal) -> 0.  None unregisters."""
+    if apply is None:
+        _check(_lib.gt_dvfs_set_backend(None))
+        _backend_refs.clear()
+        return
+    a = DVFS_APPLY(lambda user, dev, kind, value: int(apply(dev, kind, value)))
+    r = DVFS_RESTORE(lambda user, dev: int(restore(dev))) if restore else DVFS_RESTORE()
+    b = DvfsBackend(a, r, None)
+    _check(_lib.gt_dvfs_set_backend(ctypes.byref(b)))
+    _backend_refs[:] = [a, r, b]
 
 
 def dvfs_state():

@@ -11,8 +11,11 @@
 //     voltage, hotspot temperature) refreshes about once per second, so it is
 //     re-read at most every 50 ms and serves as the slow cross-check.
 // The clock knob is the graphics-clock upper limit and the power knob the
-// socket power cap, both through amd-smi.  Both need privileges; without
-// GT_INIT_ALLOW_DVFS the library refuses to change them (GT_E_PERM).
+// socket power cap.  The library itself changes no device setting: a caller
+// with the privileges registers a DVFS backend (gt_dvfs_set_backend) whose
+// apply and restore functions change the knob; the library keeps the knob's
+// state (repeated settings are no-ops, gt_shutdown restores) and refuses any
+// change without GT_INIT_ALLOW_DVFS and a backend (GT_E_PERM).
 //
 // Fake backends (for tests that must not touch the hardware):
 //   GT_INIT_FAKE_DVFS    the knob is only recorded; settable clocks 500..2400 MHz
@@ -41,12 +44,10 @@ struct Smi {
     bool open = false;
     amdsmi_processor_handle h = nullptr;
     double energy_res_j = 15.259e-6;
-    // restore state for DVFS
-    bool clk_changed = false, cap_changed = false;
-    uint64_t orig_max_clk = 0, orig_cap_uw = 0;
     uint64_t last_energy_raw = 0;
     double energy_wrap_j = 0;
     int hwmon_fd = -1;            // power1_input of this device
+    std::string hwmon_dir;        // its hwmon directory
     double metrics_t = -1;        // host time of the cached metrics read
     gt_sensor_sample cached{};    // slow fields of the last metrics read
 };
@@ -61,6 +62,8 @@ struct Fake {
 
 Smi g_smi;
 Fake g_fake;
+gt_dvfs_backend g_backend{};    // caller-supplied knob setter (none by default)
+bool g_backend_changed = false;  // the backend changed a knob since the last restore
 std::mutex g_mu;
 std::atomic<bool> g_busy{false};
 
@@ -70,12 +73,12 @@ const char *smi_str(amdsmi_status_t s) {
     return "unknown amd-smi status";
 }
 
-// Locate /sys/class/drm/cardN/device/hwmon/hwmonM/power1_input for the PCI
-// address of the HIP device; -1 if none.
-int open_hwmon_power(const DeviceInfo &d) {
+// Locate /sys/class/drm/cardN/device/hwmon/hwmonM (the one holding
+// power1_input) for the PCI address of the HIP device; "" if none.
+std::string find_hwmon_dir(const DeviceInfo &d) {
     DIR *drm = opendir("/sys/class/drm");
-    if (!drm) return -1;
-    int fd = -1;
+    if (!drm) return "";
+    std::string found;
     while (struct dirent *e = readdir(drm)) {
         if (strncmp(e->d_name, "card", 4) != 0 || strchr(e->d_name, '-')) continue;
         std::string dev = std::string("/sys/class/drm/") + e->d_name + "/device";
@@ -89,14 +92,32 @@ int open_hwmon_power(const DeviceInfo &d) {
         if (!hw) continue;
         while (struct dirent *h = readdir(hw)) {
             if (strncmp(h->d_name, "hwmon", 5) != 0) continue;
-            fd = open((dev + "/hwmon/" + h->d_name + "/power1_input").c_str(), O_RDONLY | O_CLOEXEC);
-            if (fd >= 0) break;
+            const std::string dir = dev + "/hwmon/" + h->d_name;
+            if (access((dir + "/power1_input").c_str(), R_OK) == 0) {
+                found = dir;
+                break;
+            }
         }
         closedir(hw);
-        if (fd >= 0) break;
+        if (!found.empty()) break;
     }
     closedir(drm);
-    return fd;
+    return found;
+}
+
+// One microwatt value from a hwmon file of this device, in W; NaN if absent.
+double read_hwmon_file_w(const std::string &dir, const char *name) {
+    if (dir.empty()) return NAN;
+    const int fd = open((dir + "/" + name).c_str(), O_RDONLY | O_CLOEXEC);
+    if (fd < 0) return NAN;
+    char buf[64];
+    const ssize_t n = pread(fd, buf, sizeof buf - 1, 0);
+    close(fd);
+    if (n <= 0) return NAN;
+    buf[n] = 0;
+    char *end = nullptr;
+    const double uw = strtod(buf, &end);
+    return end == buf ? NAN : uw * 1e-6;
 }
 
 double read_hwmon_w(int fd) {
@@ -144,7 +165,9 @@ int smi_open_locked() {
     float res = 0;
     if (amdsmi_get_energy_count(g_smi.h, &acc, &res, &ts) == AMDSMI_STATUS_SUCCESS && res > 0)
         g_smi.energy_res_j = res * 1e-6;
-    g_smi.hwmon_fd = open_hwmon_power(st.dev);
+    g_smi.hwmon_dir = find_hwmon_dir(st.dev);
+    g_smi.hwmon_fd = g_smi.hwmon_dir.empty() ? -1
+                                             : open((g_smi.hwmon_dir + "/power1_input").c_str(), O_RDONLY | O_CLOEXEC);
     g_smi.metrics_t = -1;
     return GT_OK;
 }
@@ -197,7 +220,31 @@ double gauss(uint64_t &state) {
     return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
 }
 
-constexpr double kFakeDefaultMhz = 2400.0;
+constexpr double kFakeDefaultMhz = 2400.0, kFakeMinMhz = 500.0;
+
+// Under a power cap the (fake) firmware runs the highest clock, on a 0.01 MHz
+// grid over 500..2400 MHz, whose loaded power P*(f) stays within the cap;
+// when even 500 MHz exceeds it, 500 MHz (the cap is then not met).  A scan
+// from the top (P* need not be monotone with the literal Eq. 3), memoised
+// per (cap, model): the sensor asks at every sample.
+double fake_capped_clock(double cap_w) {
+    static double memo_cap = -1, memo_f = 0;
+    static gt_power_model memo_model{};
+    const gt_power_model &m = g_fake.model;
+    if (cap_w == memo_cap && memcmp(&m, &memo_model, sizeof m) == 0) return memo_f;
+    double f = kFakeMinMhz;
+    for (int64_t k = (int64_t)llround((kFakeDefaultMhz - kFakeMinMhz) * 100); k >= 0; --k) {
+        const double fk = kFakeMinMhz + 0.01 * (double)k;
+        if (gt_power_model_eval(&m, fk) <= cap_w) {
+            f = fk;
+            break;
+        }
+    }
+    memo_cap = cap_w;
+    memo_model = m;
+    memo_f = f;
+    return f;
+}
 
 }  // namespace
 
@@ -230,8 +277,8 @@ int sensor_read(gt_sensor_sample *out) {
     if (st.flags & GT_INIT_FAKE_SENSOR) {
         if (!g_fake.have_model) return set_error(GT_E_SENSOR, "fake sensor: no model");
         double f = st.clock.kind == GT_CLOCK_SCLK_MHZ ? st.clock.value : kFakeDefaultMhz;
+        if (st.clock.kind == GT_CLOCK_POWER_CAP_W) f = fake_capped_clock(st.clock.value);
         double p = g_busy.load() ? gt_power_model_eval(&g_fake.model, f) : g_fake.model.p_idle;
-        if (st.clock.kind == GT_CLOCK_POWER_CAP_W) p = std::min(p, (double)st.clock.value);
         p += g_fake.noise_w * gauss(g_fake.rng);
         if (g_fake.last_t >= 0) g_fake.e_j += g_fake.last_p * (out->t_s - g_fake.last_t);
         g_fake.last_t = out->t_s;
@@ -278,28 +325,11 @@ int dvfs_apply(const gt_clock &clk) {
     if (!(st.flags & GT_INIT_ALLOW_DVFS))
         return set_error(GT_E_PERM, "DVFS changes are not enabled (gt_init flag GT_INIT_ALLOW_DVFS)");
     std::lock_guard<std::mutex> lk(g_mu);
-    int rc = smi_open_locked();
-    if (rc) return rc;
-    amdsmi_status_t s;
-    if (clk.kind == GT_CLOCK_SCLK_MHZ) {
-        if (!g_smi.clk_changed) {
-            amdsmi_clk_info_t ci;
-            if (amdsmi_get_clock_info(g_smi.h, AMDSMI_CLK_TYPE_GFX, &ci) == AMDSMI_STATUS_SUCCESS)
-                g_smi.orig_max_clk = ci.max_clk;
-        }
-        s = amdsmi_set_gpu_clk_limit(g_smi.h, AMDSMI_CLK_TYPE_GFX, CLK_LIMIT_MAX, (uint64_t)clk.value);
-        if (s == AMDSMI_STATUS_SUCCESS) g_smi.clk_changed = true;
-    } else {
-        if (!g_smi.cap_changed) {
-            amdsmi_power_cap_info_t pc;
-            if (amdsmi_get_power_cap_info(g_smi.h, 0, &pc) == AMDSMI_STATUS_SUCCESS)
-                g_smi.orig_cap_uw = pc.power_cap;
-        }
-        s = amdsmi_set_power_cap(g_smi.h, 0, (uint64_t)clk.value * 1000000ull);
-        if (s == AMDSMI_STATUS_SUCCESS) g_smi.cap_changed = true;
-    }
-    if (s == AMDSMI_STATUS_NO_PERM) return set_error(GT_E_PERM, "DVFS: permission denied");
-    if (s != AMDSMI_STATUS_SUCCESS) return set_error(GT_E_PERM, "DVFS: %s", smi_str(s));
+    if (!g_backend.apply) return set_error(GT_E_PERM, "DVFS: no backend registered (gt_dvfs_set_backend)");
+    const int rc = g_backend.apply(g_backend.user, st.dev.ordinal, clk.kind, clk.value);
+    if (rc != 0) return set_error(GT_E_PERM, "DVFS: the backend refused %s = %d (status %d)",
+                                  clk.kind == GT_CLOCK_SCLK_MHZ ? "clock limit" : "power cap", clk.value, rc);
+    g_backend_changed = true;
     st.clock = clk;
     return GT_OK;
 }
@@ -312,17 +342,11 @@ int dvfs_restore() {
     }
     std::lock_guard<std::mutex> lk(g_mu);
     int rc = GT_OK;
-    if (g_smi.open && g_smi.clk_changed && g_smi.orig_max_clk) {
-        if (amdsmi_set_gpu_clk_limit(g_smi.h, AMDSMI_CLK_TYPE_GFX, CLK_LIMIT_MAX, g_smi.orig_max_clk) !=
-            AMDSMI_STATUS_SUCCESS)
-            rc = set_error(GT_E_PERM, "DVFS restore of the clock limit failed");
-        g_smi.clk_changed = false;
+    if (g_backend_changed && g_backend.restore) {
+        const int s = g_backend.restore(g_backend.user, st.dev.ordinal);
+        if (s != 0) rc = set_error(GT_E_PERM, "DVFS: the backend's restore failed (status %d)", s);
     }
-    if (g_smi.open && g_smi.cap_changed && g_smi.orig_cap_uw) {
-        if (amdsmi_set_power_cap(g_smi.h, 0, g_smi.orig_cap_uw) != AMDSMI_STATUS_SUCCESS)
-            rc = set_error(GT_E_PERM, "DVFS restore of the power cap failed");
-        g_smi.cap_changed = false;
-    }
+    g_backend_changed = false;
     st.clock = gt_clock{GT_CLOCK_DEFAULT, 0};
     return rc;
 }
@@ -330,7 +354,7 @@ int dvfs_restore() {
 int dvfs_settable(double step_mhz, std::vector<double> &out) {
     out.clear();
     if (!(step_mhz > 0)) return set_error(GT_E_INVAL, "step must be positive");
-    double lo = 500, hi = 2400;
+    double lo = kFakeMinMhz, hi = kFakeDefaultMhz;
     if (!(state().flags & GT_INIT_FAKE_DVFS)) {
         std::lock_guard<std::mutex> lk(g_mu);
         int rc = smi_open_locked();
@@ -369,6 +393,47 @@ int gt_settable_clocks(double step_mhz, double *mhz, size_t cap, size_t *n) {
     *n = v.size();
     for (size_t i = 0; i < v.size() && i < cap; ++i) mhz[i] = v[i];
     if (v.size() > cap) return set_error(GT_E_CAPACITY, "gt_settable_clocks: %zu clocks", v.size());
+    return GT_OK;
+}
+
+int gt_dvfs_set_backend(const gt_dvfs_backend *backend) {
+    clear_error();
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_backend_changed) return set_error(GT_E_STATE, "gt_dvfs_set_backend: restore the knob first (gt_shutdown)");
+    if (backend && !backend->apply) return set_error(GT_E_INVAL, "gt_dvfs_set_backend: apply is required");
+    g_backend = backend ? *backend : gt_dvfs_backend{};
+    return GT_OK;
+}
+
+int gt_power_cap_range(double *min_w, double *max_w, double *current_w) {
+    clear_error();
+    if (!min_w || !max_w || !current_w) return set_error(GT_E_INVAL, "gt_power_cap_range: null argument");
+    if (!state().inited) return set_error(GT_E_STATE, "gt_power_cap_range: call gt_init first");
+    if (state().flags & GT_INIT_FAKE_DVFS) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!g_fake.have_model)
+            return set_error(GT_E_SENSOR, "gt_power_cap_range: fake DVFS needs gt_fake_sensor_model");
+        // fake range: half the model's P_max up to P_max
+        *min_w = 0.5 * g_fake.model.p_max;
+        *max_w = g_fake.model.p_max;
+        *current_w = state().clock.kind == GT_CLOCK_POWER_CAP_W ? (double)state().clock.value : *max_w;
+        return GT_OK;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    int rc = smi_open_locked();
+    if (rc) return rc;
+    // amd-smi first; fields it leaves at 0 come from the hwmon files
+    // power1_cap_min / power1_cap_max / power1_cap; NaN where neither knows
+    amdsmi_power_cap_info_t pc{};
+    const bool smi_ok = amdsmi_get_power_cap_info(g_smi.h, 0, &pc) == AMDSMI_STATUS_SUCCESS;
+    auto pick = [&](uint64_t smi_uw, const char *file) {
+        return smi_ok && smi_uw > 0 ? smi_uw * 1e-6 : read_hwmon_file_w(g_smi.hwmon_dir, file);
+    };
+    *min_w = pick(pc.min_power_cap, "power1_cap_min");
+    *max_w = pick(pc.max_power_cap, "power1_cap_max");
+    *current_w = pick(pc.power_cap, "power1_cap");
+    if (std::isnan(*min_w) && std::isnan(*max_w) && std::isnan(*current_w))
+        return set_error(GT_E_SENSOR, "power cap: neither amd-smi nor hwmon reports it");
     return GT_OK;
 }
 

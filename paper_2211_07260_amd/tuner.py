@@ -308,6 +308,52 @@ def tuning_methods(measure, configs, settable, f_base=None):
     return out
 
 
+# ---- power capping versus clock tuning (section V.C) ----
+
+def equidistant(lo, hi, n=7):
+    """n equally spaced knob values from lo to hi, both included (the paper
+    samples each knob's range at 7 points)."""
+    if n < 2:
+        return [float(hi)]
+    return [lo + (hi - lo) * k / (n - 1) for k in range(n)]
+
+
+def knob_search(measure, configs, knobs):
+    """Every config at every knob value; the lowest-energy point (ties: time,
+    then the earlier config, then the earlier knob, as gt_select orders).
+    measure(config, knob) -> dict with t_run_s and e_run_j."""
+    rows = []
+    for cfg in configs:
+        for k in knobs:
+            rows.append({"config": list(gt.as_config(cfg).as_tuple()), "knob": k, **measure(cfg, k)})
+    recs = [{"t_run_s": r["t_run_s"], "e_run_j": r["e_run_j"]} for r in rows]
+    return {"rows": rows, "best": rows[gt.select(recs, "energy")], "points": len(rows)}
+
+
+def cap_vs_clock(measure_clock, measure_cap, configs, clocks, caps):
+    """Section V.C: the same configs searched once with the clock as the extra
+    tunable and once with the power cap; the lowest energy each reaches.
+    measure_clock(config, mhz), measure_cap(config, watts) -> dicts with
+    t_run_s, e_run_j (and, for the power-versus-clock view, p_median_w and
+    sclk_act_mhz)."""
+    by_clock = knob_search(measure_clock, configs, clocks)
+    by_cap = knob_search(measure_cap, configs, caps)
+    e_clk, e_cap = by_clock["best"]["e_run_j"], by_cap["best"]["e_run_j"]
+    return {"clock": by_clock, "cap": by_cap, "clocks_mhz": list(clocks), "caps_w": list(caps),
+            "energy_cap_over_clock": e_cap / e_clk}
+
+
+def load_power_views(kind, buf, clocks, caps, window_s=1.0, discard_s=0.3):
+    """The power-versus-clock view of a synthetic full load under each knob
+    (the paper's Fig. 6): for every clock limit and every power cap, the
+    clock the device ran and the power it drew.  kind: gt.LOAD_*."""
+    def one(clk):
+        m = gt.measure_load(kind, buf, clk, window_s=window_s, discard_s=discard_s)
+        return {"sclk_act_mhz": m["sclk_act_mhz"], "p_median_w": m["p_median_w"], "rate": m["gflops"]}
+    return {"by_clock": [{"clock_mhz": f, **one(gt.clock(gt.CLOCK_SCLK_MHZ, int(f)))} for f in clocks],
+            "by_cap": [{"cap_w": c, **one(gt.clock(gt.CLOCK_POWER_CAP_W, int(c)))} for c in caps]}
+
+
 def hardware_measure(problem, d_in, d_w, d_out, window_s=1.0, discard_s=0.3):
     """measure(config, clock) over the real DVFS knob (needs privileges)."""
     def measure(cfg, f_mhz):

@@ -22,7 +22,7 @@ def header_functions():
         src = open(os.path.join(ROOT, "include", h)).read()
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
         src = re.sub(r"//[^\n]*", "", src)
-        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*(?:\s+|\s*\*\s*)([A-Za-z_][A-Za-z0-9_]*)\s*\(",
                              src, flags=re.M):
             names.append(m.group(1))
     return sorted(set(names))
@@ -228,3 +228,13 @@ def test_fit_rejects_bad_input():
         gt.fit_power_model([1000, 2000, 1500], [100, 200, 150], 1000.0)  # too few for Eq. 3
     with pytest.raises(gt.GreentuneError):
         gt.fit_power_model([1000, -5, 1500, 1200], [100, 200, 150, 120], 1000.0)
+
+
+def test_dvfs_backend_registration_rules():
+    # the library changes no device setting itself: knob changes go through a
+    # caller-registered backend, which needs an apply function
+    import ctypes
+    b = gt.DvfsBackend(gt.DVFS_APPLY(), gt.DVFS_RESTORE(), None)
+    assert gt.lib().gt_dvfs_set_backend(ctypes.byref(b)) == gt.GT_E_INVAL
+    gt.set_dvfs_backend(lambda dev, kind, value: 0, lambda dev: 0)
+    gt.set_dvfs_backend(None)

@@ -4,6 +4,8 @@ kernel launches and HIP-event timing, synthetic power from a known Eq. 2/3
 model at the requested clock.  Checks the median-power energy arithmetic,
 the clock bookkeeping, the fit recovering the model from <= 5 readings, and
 that without the fake backend a clock request is refused."""
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -131,5 +133,78 @@ def test_fake_dvfs_calibration_with_synthetic_loads(gt):
                                           window_s=0.05, discard_s=0.01)
         rep = tuner.steered_search(measure, [(32, 8, 4, 2, 0, 0)], settable, MODEL["p_max"], model=cal["model"])
         assert rep["fit_points"] == [] and rep["band_mhz"]
+    finally:
+        gt.shutdown()
+
+
+def test_fake_power_cap_runs_the_highest_clock_that_fits(gt):
+    # under a cap the fake firmware runs the highest clock (0.01 MHz grid over
+    # 500..2400) whose model power fits; below the lowest clock's power the cap
+    # is not met and the clock sits at 500 MHz
+    import numpy as np
+    from oracle import power_model as opm
+    capped = dict(p_idle=240.0, alpha=0.35, beta=1.2e-3, tau=1250.0, p_max=1400.0)
+    grid = 500.0 + 0.01 * np.arange(190001)
+    p_grid = opm.power(grid, capped["p_idle"], capped["alpha"], capped["beta"], capped["tau"], capped["p_max"])
+    gt.init(0, gt.INIT_FAKE_SENSOR | gt.INIT_FAKE_DVFS)
+    try:
+        m = gt.power_model(capped["p_idle"], capped["alpha"], capped["beta"], capped["tau"], capped["p_max"])
+        gt.fake_sensor_model(m, noise_w=0.0)
+        lo, hi, cur = gt.power_cap_range()
+        assert (lo, hi, cur) == (700.0, 1400.0, 1400.0)
+        buf = torch.empty(1 << 22, dtype=torch.float32, device=torch.device("cuda:0"))
+        for cap in (700, 883, 1050, 1233, 1400, 300):
+            r = gt.measure_load(gt.LOAD_FP32_FMA, buf, gt.clock(gt.CLOCK_POWER_CAP_W, cap), window_s=0.1,
+                                discard_s=0.02)
+            ok = grid[p_grid <= cap]
+            want = ok[-1] if len(ok) else 500.0
+            assert r["sclk_act_mhz"] == pytest.approx(want, abs=0.011), cap
+            assert r["p_median_w"] == pytest.approx(gt.power_model_eval(m, r["sclk_act_mhz"]), rel=1e-12)
+            assert r["p_median_w"] <= cap or want == 500.0
+        assert gt.power_cap_range()[2] == 300.0
+    finally:
+        gt.shutdown()
+
+
+def test_power_cap_range_reads_on_the_device(gt):
+    # the real amd-smi power-cap range (readable without privileges)
+    gt.init(0, 0)
+    try:
+        lo, hi, cur = gt.power_cap_range()
+        print("power cap range: min %.1f W, max %.1f W, in force %.1f W" % (lo, hi, cur))
+        assert cur > 0
+        if not (math.isnan(lo) or math.isnan(hi)):
+            assert 0 <= lo <= cur <= hi
+    finally:
+        gt.shutdown()
+
+
+def test_dvfs_requests_go_through_the_registered_backend(gt):
+    # the library changes no device setting: with GT_INIT_ALLOW_DVFS a clock
+    # request calls the caller's backend (a recorder here, so nothing changes
+    # on the device), repeats are no-ops, and shutdown calls its restore
+    calls = []
+    gt.set_dvfs_backend(lambda dev, kind, value: calls.append(("apply", dev, kind, value)) or 0,
+                        lambda dev: calls.append(("restore", dev)) or 0)
+    try:
+        gt.init(0, gt.INIT_ALLOW_DVFS)
+        buf = torch.empty(1 << 22, dtype=torch.float32, device=torch.device("cuda:0"))
+        for _ in range(2):
+            gt.measure_load(gt.LOAD_COPY, buf, gt.clock(gt.CLOCK_SCLK_MHZ, 1500), window_s=0.05, discard_s=0.01)
+        gt.measure_load(gt.LOAD_COPY, buf, gt.clock(gt.CLOCK_POWER_CAP_W, 900), window_s=0.05, discard_s=0.01)
+        assert gt.dvfs_state() == (True, (gt.CLOCK_POWER_CAP_W, 900))
+        gt.shutdown()
+        assert calls == [("apply", 0, gt.CLOCK_SCLK_MHZ, 1500), ("apply", 0, gt.CLOCK_POWER_CAP_W, 900),
+                         ("restore", 0)]
+    finally:
+        gt.shutdown()
+        gt.set_dvfs_backend(None)
+    # without a backend the request is refused
+    gt.init(0, gt.INIT_ALLOW_DVFS)
+    try:
+        buf = torch.empty(1 << 22, dtype=torch.float32, device=torch.device("cuda:0"))
+        with pytest.raises(gt.GreentuneError) as e:
+            gt.measure_load(gt.LOAD_COPY, buf, gt.clock(gt.CLOCK_SCLK_MHZ, 1500), window_s=0.05, discard_s=0.01)
+        assert e.value.code == gt.GT_E_PERM
     finally:
         gt.shutdown()
