@@ -525,7 +525,7 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
     // cores idle.  (With weights read from L2, each weight load would wait
     // behind the stores: loads and stores share one in-order counter.)
     constexpr bool DEFER = UNROLLED && WP != kWeightsL2 && TH == 4 && NZ <= 10 && S <= 5;
-    constexpr int NQ = kMT * NT;              // 16-byte stores per lane and tile
+    constexpr int NQ = kMT * NT / 2;          // store pairs per lane and tile
     constexpr int ZS = NZ < 4 ? NZ : 4;        // passes they are spread over
     constexpr int QPZ = (NQ + ZS - 1) / ZS;    // ... per pass
     constexpr int QPS = (QPZ + NS - 1) / NS;   // ... per step
@@ -534,11 +534,31 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
     constexpr int PF_Z = NZ >= 2 ? NZ - 2 : 0;
     f32x4 sv[kMT][NT];
     bool pending = false;  // sv holds a tile's results still to be stored (wave-uniform)
-    float *sv_dst = a.out;
-    int sv_xl = 0;  // M-tiles m < sv_xl of this lane are inside the output row
+    // Full-line stores: a lane holds 4 channels (16 bytes) of one pixel per
+    // N-tile, so one store instruction would write half of each 128-byte line
+    // (16 channels of 16 pixels).  Adjacent lanes (pixels 4*li and 4*li + 4
+    // of an M-tile) swap one N-tile of a pair (j, j+1) through DPP; then the
+    // pair's first store writes 32 channels (one whole line) of the even
+    // lane's pixel for 8 pixels, and the second those of the odd lane's pixel.
+    float *sv_dst = a.out;    // even lane's pixel, this lane's channel slot
+    int sv_xl0 = 0, sv_xl1 = 0;  // M-tiles m < sv_xl0 (sv_xl1) of the even (odd) lane's pixel are inside the row
+    const bool odd = li & 1;
     auto store_q = [&](int q) {
-        const int m = q / NT, j = q - m * NT;
-        if (m < sv_xl) __builtin_nontemporal_store(sv[m][j], reinterpret_cast<f32x4 *>(sv_dst + (size_t)m * a.c_out + 16 * j));
+        const int m = q / (NT / 2), j = 2 * (q - m * (NT / 2));
+        const f32x4 send = odd ? sv[m][j] : sv[m][j + 1];
+        f32x4 recv;
+        // quad_perm [1,0,3,2]: swap with the adjacent lane.  Each element goes
+        // through a scalar first: hipcc's __builtin_bit_cast of a vector
+        // element (send[e]) reads element 0 whatever e is.
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float se = send[e];
+            recv[e] = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(se), 0xB1, 0xF, 0xF, true));
+        }
+        const f32x4 first = odd ? recv : sv[m][j], second = odd ? sv[m][j + 1] : recv;
+        float *dst = sv_dst + (size_t)m * a.c_out + 16 * j;
+        if (m < sv_xl0) __builtin_nontemporal_store(first, reinterpret_cast<f32x4 *>(dst));
+        if (m < sv_xl1) __builtin_nontemporal_store(second, reinterpret_cast<f32x4 *>(dst + 4 * (size_t)a.c_out));
     };
 
     for (int t = t_begin; t < t_end; ++t) {
@@ -697,11 +717,15 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
         }
 
         // D[i = 4*lg + e][n = li] of tiles (m, j): output channel n_blk +
-        // 16*j + 4*lg + e of pixel x0 + 4*li + m
+        // 16*j + 4*lg + e of pixel x0 + 4*li + m; stored in pairs (see
+        // store_q): the even lane of a pair writes channels 16*j + 4*lg of
+        // both pixels, the odd lane channels 16*(j+1) + 4*lg
         const int y = y0 + wave;
         pending = y < a.out_h;
-        sv_dst = a.out + (((size_t)b * a.out_h + y) * a.out_w + x0 + 4 * li) * a.c_out + n_blk + 4 * lg;
-        sv_xl = min(kMT, a.out_w - (x0 + 4 * li));
+        const int xe = x0 + 4 * (li & ~1);
+        sv_dst = a.out + (((size_t)b * a.out_h + y) * a.out_w + xe) * a.c_out + n_blk + 16 * (li & 1) + 4 * lg;
+        sv_xl0 = min(kMT, a.out_w - xe);
+        sv_xl1 = min(kMT, a.out_w - (xe + 4));
 #pragma unroll
         for (int m = 0; m < kMT; ++m)
 #pragma unroll
