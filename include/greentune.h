@@ -252,6 +252,13 @@ int gt_sensor_busy(int busy);
  * at step_mhz spacing; the fake DVFS backend reports 500..2400).
  * GT_E_CAPACITY if cap is too small (*n still written). */
 int gt_settable_clocks(double step_mhz, double *mhz, size_t cap, size_t *n);
+/* Stale-sensor test on a power trace (times ascending, s; readings, W):
+ * 1 when the trace spans at least min_span_s and every reading equals the
+ * first, else 0 (negative error code on bad arguments).  measure_time_energy
+ * and measure_load apply it to the kept window of the hardware sensor with a
+ * 0.5 s span and fail with GT_E_SENSOR on a stale reading. */
+int gt_sensor_stale(const double *t_s, const double *p_w, size_t n, double min_span_s);
+
 /* DVFS backend: the library changes no device setting itself.  A caller
  * with the privileges to change the graphics-clock limit or the socket power
  * cap (the two knobs of sections III.C and V.C) registers functions that do
@@ -261,7 +268,12 @@ int gt_settable_clocks(double step_mhz, double *mhz, size_t cap, size_t *n);
  * changes, and gt_shutdown calls restore(user, device_ordinal) (may be
  * NULL) to return the device to its defaults.  The structure is copied;
  * NULL unregisters.  GT_E_STATE while a knob set through the backend is
- * still in force.  Without a backend, DVFS requests fail with GT_E_PERM. */
+ * still in force.  Without a backend, DVFS requests fail with GT_E_PERM.
+ * Before each apply the library records the knob in a state file
+ * ($TMPDIR or /tmp, greentune-dvfs-<pci domain>-<bus>-<device>.state),
+ * removed after a successful restore; gt_init with GT_INIT_ALLOW_DVFS finds
+ * a file a crashed process left and calls restore first (GT_E_STATE if no
+ * backend with a restore function is registered then). */
 typedef struct {
     int (*apply)(void *user, int32_t device_ordinal, int32_t kind, int32_t value);
     int (*restore)(void *user, int32_t device_ordinal);

@@ -151,6 +151,7 @@ def _load():
         "gt_dvfs_state": ([P(Clock)], c_int),
         "gt_power_cap_range": ([P(c_double), P(c_double), P(c_double)], c_int),
         "gt_dvfs_set_backend": ([P(DvfsBackend)], c_int),
+        "gt_sensor_stale": ([P(c_double), P(c_double), c_size, c_double], c_int),
         "gt_fake_sensor_model": ([P(PowerModel), c_double, ctypes.c_uint64], c_int),
         "gt_roofline_probe": ([vp, c_size, vp, P(c_double), P(c_double)], c_int),
         "gt_mfma_probe": ([vp, c_size, vp, P(c_double), P(c_double)], c_int),
@@ -179,7 +180,7 @@ _lib = _load()
 EXPORTED = ("gt_init", "gt_shutdown", "gt_last_error", "gt_version", "conv2d_run",
             "tune_space_enumerate", "measure_time_energy", "measure_load", "fit_power_model", "gt_power_model_eval", "gt_power_model_throttle_clock",
             "gt_power_model_band", "gt_energy_from_samples", "gt_select", "gt_problem_flops",
-            "gt_conv_lds_bytes", "gt_sensor_read", "gt_settable_clocks", "gt_dvfs_state", "gt_power_cap_range", "gt_dvfs_set_backend",
+            "gt_conv_lds_bytes", "gt_sensor_read", "gt_settable_clocks", "gt_dvfs_state", "gt_power_cap_range", "gt_dvfs_set_backend", "gt_sensor_stale",
             "gt_fake_sensor_model", "gt_roofline_probe", "gt_mfma_probe", "gt_batch_pack", "conv2d_run_batched",
             "gt_graph_begin", "gt_graph_end", "gt_graph_launch", "gt_graph_destroy", "gt_sampler_start",
             "gt_sampler_stop", "gt_sensor_busy", "gt_ffg_centrality")
@@ -379,6 +380,18 @@ def settable_clocks(step_mhz=25.0):
     return [arr[k] for k in range(n.value)]
 
 
+def sensor_stale(t_s, p_w, min_span_s=0.5):
+    """True when a power trace spanning >= min_span_s never changes."""
+    ta, n = _darr(t_s)
+    pa, n2 = _darr(p_w)
+    if n != n2:
+        raise ValueError("t and p differ in length")
+    rc = _lib.gt_sensor_stale(ta, pa, n, float(min_span_s))
+    if rc < 0:
+        _check(rc)
+    return rc == 1
+
+
 def power_cap_range():
     """(min, max, current) power cap in W (amd-smi, or the fake backend's)."""
     lo, hi, cur = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
@@ -401,6 +414,9 @@ def set_dvfs_backend(apply, restore=None):
     r = DVFS_RESTORE(lambda user, dev: int(restore(dev))) if restore else DVFS_RESTORE()
     b = DvfsBackend(a, r, None)
     _check(_lib.gt_dvfs_set_backend(ctypes.byref(b)))
+    if not _backend_refs:
+        import atexit
+        atexit.register(_lib.gt_shutdown)  # restore the knob on a normal exit
     _backend_refs[:] = [a, r, b]
 
 

@@ -118,6 +118,13 @@ int gt_init(int device_ordinal, uint32_t flags) {
     }
     st.clock = gt_clock{GT_CLOCK_DEFAULT, 0};
     st.inited = true;
+    if ((flags & GT_INIT_ALLOW_DVFS) && !(flags & (GT_INIT_FAKE_DVFS | GT_INIT_HOST_ONLY))) {
+        const int rc = dvfs_recover();
+        if (rc) {
+            st.inited = false;
+            return rc;
+        }
+    }
     return GT_OK;
 }
 

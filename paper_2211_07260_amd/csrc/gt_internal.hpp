@@ -64,6 +64,8 @@ int sensor_read(gt_sensor_sample *s);
 void sensor_set_busy(bool busy);         // fake sensor: kernel activity in progress
 int dvfs_apply(const gt_clock &clk);     // no-op when equal to the current knob
 int dvfs_restore();
+int dvfs_recover();                       // restore a knob a previous process left set (state file)
+std::string dvfs_state_path();            // that process's record of the knob in force
 int dvfs_settable(double step_mhz, std::vector<double> &out);
 double dvfs_requested_mhz();             // 0 when the clock is at its default
 

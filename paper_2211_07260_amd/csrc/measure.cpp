@@ -31,6 +31,10 @@ struct EventPair {
 
 namespace gt {
 
+// A kept window at least this long whose power never changes is stale: the
+// socket power reading refreshes every few milliseconds under load.
+constexpr double kStaleSpanS = 0.5;
+
 // The measurement window shared by measure_time_energy and measure_load:
 // warm-up launches, an estimate of the launch time, then launches back to
 // back for the window while the sampler records the sensor.
@@ -101,13 +105,14 @@ int measure_window(const std::function<int(hipStream_t)> &launch, double flops_p
     GT_HIP_CHECK(hipEventElapsedTime(&win_ms, win.a, win.b));
 
     // keep the samples after the stabilisation discard
-    std::vector<double> kept_p;
+    std::vector<double> kept_p, kept_t;
     double sclk_sum = 0;
     int sclk_n = 0;
     for (const gt_sensor_sample &smp : samples) {
         if (smp.t_s < t_start + o.discard_s || smp.t_s > t_stop) continue;
         if (!std::isfinite(smp.power_w)) continue;
         kept_p.push_back(smp.power_w);
+        kept_t.push_back(smp.t_s);
         if (std::isfinite(smp.sclk_mhz)) {
             sclk_sum += smp.sclk_mhz;
             ++sclk_n;
@@ -116,6 +121,12 @@ int measure_window(const std::function<int(hipStream_t)> &launch, double flops_p
     if (kept_p.empty())
         return set_error(GT_E_SENSOR, "measure: no power sample in the kept window (%zu samples, sensor errors %d)",
                          samples.size(), sensor_err.load());
+    // a hardware power reading that never changes under load is stale (the
+    // fake sensor without noise is constant by design)
+    if (!(state().flags & GT_INIT_FAKE_SENSOR) &&
+        gt_sensor_stale(kept_t.data(), kept_p.data(), kept_p.size(), kStaleSpanS) == 1)
+        return set_error(GT_E_SENSOR, "measure: stale sensor, power unchanged at %.1f W over %.2f s (%zu samples)",
+                         kept_p[0], kept_t.back() - kept_t[0], kept_p.size());
     gt_measurement &m = *rec;
     m = gt_measurement();
     m.launches = launched;
@@ -158,6 +169,15 @@ int measure_window(const std::function<int(hipStream_t)> &launch, double flops_p
 }
 
 }  // namespace gt
+
+extern "C" int gt_sensor_stale(const double *t_s, const double *p_w, size_t n, double min_span_s) {
+    clear_error();
+    if (n && (!t_s || !p_w)) return set_error(GT_E_INVAL, "gt_sensor_stale: null argument");
+    if (n < 2 || !(t_s[n - 1] - t_s[0] >= min_span_s)) return 0;
+    for (size_t k = 1; k < n; ++k)
+        if (p_w[k] != p_w[0]) return 0;
+    return 1;
+}
 
 extern "C" int measure_time_energy(const gt_problem *problem, const gt_conv_config *config,
                                    gt_clock clock, const gt_measure_opts *opts, const void *d_in,

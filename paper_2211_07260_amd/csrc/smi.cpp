@@ -246,6 +246,15 @@ double fake_capped_clock(double cap_w) {
     return f;
 }
 
+// Record the knob about to be set (kind and value, one line).
+bool write_state_file(const gt_clock &clk) {
+    const std::string path = dvfs_state_path();
+    FILE *f = fopen(path.c_str(), "w");
+    if (!f) return false;
+    const bool ok = fprintf(f, "%d %d\n", clk.kind, clk.value) > 0;
+    return fclose(f) == 0 && ok;
+}
+
 }  // namespace
 
 int sensor_open() {
@@ -326,6 +335,9 @@ int dvfs_apply(const gt_clock &clk) {
         return set_error(GT_E_PERM, "DVFS changes are not enabled (gt_init flag GT_INIT_ALLOW_DVFS)");
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_backend.apply) return set_error(GT_E_PERM, "DVFS: no backend registered (gt_dvfs_set_backend)");
+    // the state file goes first, so that a crash after the change still
+    // leaves a record for the next gt_init to restore from
+    if (!write_state_file(clk)) return set_error(GT_E_PERM, "DVFS: cannot write %s", dvfs_state_path().c_str());
     const int rc = g_backend.apply(g_backend.user, st.dev.ordinal, clk.kind, clk.value);
     if (rc != 0) return set_error(GT_E_PERM, "DVFS: the backend refused %s = %d (status %d)",
                                   clk.kind == GT_CLOCK_SCLK_MHZ ? "clock limit" : "power cap", clk.value, rc);
@@ -344,11 +356,36 @@ int dvfs_restore() {
     int rc = GT_OK;
     if (g_backend_changed && g_backend.restore) {
         const int s = g_backend.restore(g_backend.user, st.dev.ordinal);
-        if (s != 0) rc = set_error(GT_E_PERM, "DVFS: the backend's restore failed (status %d)", s);
+        if (s != 0)
+            rc = set_error(GT_E_PERM, "DVFS: the backend's restore failed (status %d)", s);
+        else
+            unlink(dvfs_state_path().c_str());
     }
     g_backend_changed = false;
     st.clock = gt_clock{GT_CLOCK_DEFAULT, 0};
     return rc;
+}
+
+std::string dvfs_state_path() {
+    const DeviceInfo &d = state().dev;
+    const char *dir = getenv("TMPDIR");
+    char name[96];
+    snprintf(name, sizeof name, "/greentune-dvfs-%04x-%02x-%02x.state", d.pci_domain, d.pci_bus, d.pci_device);
+    return std::string(dir && *dir ? dir : "/tmp") + name;
+}
+
+int dvfs_recover() {
+    const std::string path = dvfs_state_path();
+    if (access(path.c_str(), F_OK) != 0) return GT_OK;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_backend.restore)
+        return set_error(GT_E_STATE, "DVFS: %s records a knob left set by an earlier process; register a "
+                         "backend with a restore function before gt_init", path.c_str());
+    const int s = g_backend.restore(g_backend.user, state().dev.ordinal);
+    if (s != 0) return set_error(GT_E_PERM, "DVFS: restoring the knob recorded in %s failed (status %d)",
+                                 path.c_str(), s);
+    unlink(path.c_str());
+    return GT_OK;
 }
 
 int dvfs_settable(double step_mhz, std::vector<double> &out) {

@@ -238,3 +238,12 @@ def test_dvfs_backend_registration_rules():
     assert gt.lib().gt_dvfs_set_backend(ctypes.byref(b)) == gt.GT_E_INVAL
     gt.set_dvfs_backend(lambda dev, kind, value: 0, lambda dev: 0)
     gt.set_dvfs_backend(None)
+
+
+def test_sensor_stale_rule():
+    t = [0.0, 0.2, 0.4, 0.6]
+    assert gt.sensor_stale(t, [900.0] * 4, 0.5)            # unchanged over 0.6 s
+    assert not gt.sensor_stale(t, [900.0, 900.0, 901.0, 900.0], 0.5)
+    assert not gt.sensor_stale(t[:3], [900.0] * 3, 0.5)     # spans only 0.4 s
+    assert not gt.sensor_stale([0.0], [900.0], 0.0)         # one reading proves nothing
+    assert not gt.sensor_stale([], [], 0.5)

@@ -208,3 +208,37 @@ def test_dvfs_requests_go_through_the_registered_backend(gt):
         assert e.value.code == gt.GT_E_PERM
     finally:
         gt.shutdown()
+
+
+def test_dvfs_state_file_and_recovery(gt, tmp_path, monkeypatch):
+    # the knob in force is recorded before the backend changes it and removed
+    # after restore; a record left by a crashed process is restored by the
+    # next gt_init (and refused when no backend can restore it)
+    monkeypatch.setenv("TMPDIR", str(tmp_path))
+    calls = []
+    gt.set_dvfs_backend(lambda dev, kind, value: calls.append(("apply", kind, value)) or 0,
+                        lambda dev: calls.append(("restore",)) or 0)
+    try:
+        gt.init(0, gt.INIT_ALLOW_DVFS)
+        buf = torch.empty(1 << 22, dtype=torch.float32, device=torch.device("cuda:0"))
+        gt.measure_load(gt.LOAD_COPY, buf, gt.clock(gt.CLOCK_SCLK_MHZ, 1700), window_s=0.05, discard_s=0.01)
+        files = list(tmp_path.glob("greentune-dvfs-*.state"))
+        assert len(files) == 1 and files[0].read_text().split() == [str(gt.CLOCK_SCLK_MHZ), "1700"]
+        record = files[0].read_text()
+        gt.shutdown()
+        assert not files[0].exists() and calls == [("apply", gt.CLOCK_SCLK_MHZ, 1700), ("restore",)]
+        files[0].write_text(record)          # as a crashed process would have left it
+        calls.clear()
+        gt.init(0, gt.INIT_ALLOW_DVFS)
+        assert calls == [("restore",)] and not files[0].exists()
+        gt.shutdown()
+        files[0].write_text(record)
+    finally:
+        gt.shutdown()
+        gt.set_dvfs_backend(None)
+    with pytest.raises(gt.GreentuneError) as e:
+        gt.init(0, gt.INIT_ALLOW_DVFS)
+    assert e.value.code == gt.GT_E_STATE
+    files[0].unlink()
+    gt.init(0, gt.INIT_ALLOW_DVFS)
+    gt.shutdown()
