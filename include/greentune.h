@@ -174,6 +174,19 @@ const char *gt_version(void);
 int conv2d_run(const gt_problem *problem, const gt_conv_config *config, gt_clock clock,
                const void *d_in, const void *d_filt, void *d_out, void *hip_stream);
 
+/* One part of a convolution: the work of conv2d_run split into n_parts
+ * contiguous ranges of the kernel's output tiles (part k covers tiles
+ * [T*k/n, T*(k+1)/n) of T), so that a long convolution can be issued in
+ * pieces between which other work runs (the serving form).  Every output
+ * element belongs to exactly one part and is computed exactly as by
+ * conv2d_run; the parts may run in any order, on any streams, once each.
+ * n_parts > 1 is for GT_IGEMM_BF16_MFMA on its LDS-staged kernel (square
+ * filter of an instantiated size, c_in 32 or 64, 16-byte aligned output);
+ * otherwise GT_E_UNSUPPORTED.  n_parts == 1 is conv2d_run.  GT_E_INVAL for
+ * part outside [0, n_parts). */
+int conv2d_run_part(const gt_problem *problem, const gt_conv_config *config, gt_clock clock, int32_t part,
+                    int32_t n_parts, const void *d_in, const void *d_filt, void *d_out, void *hip_stream);
+
 /* Enumerate the restricted tune space (section IV) into out[0..capacity).
  * *n_total always receives the full count; GT_E_CAPACITY if capacity is too
  * small (call with capacity 0 to size the array). */

@@ -132,6 +132,7 @@ def _load():
         "gt_last_error": ([], ctypes.c_char_p),
         "gt_version": ([], ctypes.c_char_p),
         "conv2d_run": ([P(Problem), P(ConvConfig), Clock, vp, vp, vp, vp], c_int),
+        "conv2d_run_part": ([P(Problem), P(ConvConfig), Clock, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp], c_int),
         "tune_space_enumerate": ([P(Problem), P(SpaceDesc), P(ConvConfig), c_size, P(c_size)], c_int),
         "measure_time_energy": ([P(Problem), P(ConvConfig), Clock, P(MeasureOpts), vp, vp, vp, vp,
                                  P(Measurement)], c_int),
@@ -177,7 +178,7 @@ def _load():
 
 
 _lib = _load()
-EXPORTED = ("gt_init", "gt_shutdown", "gt_last_error", "gt_version", "conv2d_run",
+EXPORTED = ("gt_init", "gt_shutdown", "gt_last_error", "gt_version", "conv2d_run", "conv2d_run_part",
             "tune_space_enumerate", "measure_time_energy", "measure_load", "fit_power_model", "gt_power_model_eval", "gt_power_model_throttle_clock",
             "gt_power_model_band", "gt_energy_from_samples", "gt_select", "gt_problem_flops",
             "gt_conv_lds_bytes", "gt_sensor_read", "gt_settable_clocks", "gt_dvfs_state", "gt_power_cap_range", "gt_dvfs_set_backend", "gt_sensor_stale",
@@ -258,6 +259,13 @@ def version():
 def conv2d_run(problem, cfg, inp, filt, out, clk=None, stream=None):
     _check(_lib.conv2d_run(ctypes.byref(problem), ctypes.byref(as_config(cfg)), clk or clock(),
                            _ptr(inp), _ptr(filt), _ptr(out), _stream(stream)))
+
+
+def conv2d_run_part(problem, cfg, part, n_parts, inp, filt, out, clk=None, stream=None):
+    """Part `part` of `n_parts` of conv2d_run (contiguous ranges of output
+    tiles; bit-identical to the whole run)."""
+    _check(_lib.conv2d_run_part(ctypes.byref(problem), ctypes.byref(as_config(cfg)), clk or clock(), int(part),
+                                int(n_parts), _ptr(inp), _ptr(filt), _ptr(out), _stream(stream)))
 
 
 def tune_space_enumerate(problem, values, max_threads=0, lds_limit=0, dedup_direct=True):

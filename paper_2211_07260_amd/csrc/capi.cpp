@@ -155,6 +155,26 @@ int conv2d_run(const gt_problem *problem, const gt_conv_config *config, gt_clock
     return launch_problem(*problem, *config, d_in, d_filt, d_out, (hipStream_t)hip_stream);
 }
 
+int conv2d_run_part(const gt_problem *problem, const gt_conv_config *config, gt_clock clock, int32_t part,
+                    int32_t n_parts, const void *d_in, const void *d_filt, void *d_out, void *hip_stream) {
+    clear_error();
+    if (!problem || !config || !d_in || !d_filt || !d_out)
+        return set_error(GT_E_INVAL, "conv2d_run_part: null argument");
+    if (n_parts < 1 || part < 0 || part >= n_parts)
+        return set_error(GT_E_INVAL, "conv2d_run_part: part %d of %d", part, n_parts);
+    if (!state().inited) return set_error(GT_E_STATE, "conv2d_run_part: call gt_init first");
+    if (state().flags & GT_INIT_HOST_ONLY)
+        return set_error(GT_E_STATE, "conv2d_run_part: library initialised host-only");
+    int rc = validate_problem_config(*problem, *config);
+    if (rc) return rc;
+    if (n_parts > 1 && problem->kind != GT_IGEMM_BF16_MFMA)
+        return set_error(GT_E_UNSUPPORTED, "conv2d_run_part: parts are for the BF16 implicit GEMM only");
+    rc = dvfs_apply(clock);
+    if (rc) return rc;
+    if (n_parts == 1) return launch_problem(*problem, *config, d_in, d_filt, d_out, (hipStream_t)hip_stream);
+    return launch_igemm(*problem, *config, d_in, d_filt, d_out, (hipStream_t)hip_stream, part, n_parts);
+}
+
 int tune_space_enumerate(const gt_problem *problem, const gt_space_desc *space,
                          gt_conv_config *out, size_t capacity, size_t *n_total) {
     clear_error();

@@ -49,7 +49,7 @@ int launch_xcorr_f32(const gt_problem &p, const gt_conv_config &c, const void *i
                      void *out, hipStream_t s);
 int validate_igemm(const gt_problem &p, const gt_conv_config &c);
 int launch_igemm(const gt_problem &p, const gt_conv_config &c, const void *in, const void *w,
-                 void *out, hipStream_t s);
+                 void *out, hipStream_t s, int part = 0, int n_parts = 1);
 int validate_problem_config(const gt_problem &p, const gt_conv_config &c);
 // synthetic full loads (roofline_probe.hip): work per launch, and one launch
 int load_work(int kind, size_t bytes, double *work);

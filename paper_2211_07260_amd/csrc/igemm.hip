@@ -364,7 +364,8 @@ struct HaloRows {
 // done with the rows they replace.
 // TH output rows (= waves) per workgroup; WM: weight placement (WeightMode).
 template <int C, int NT, int R, int S, int TH, int WM>
-__global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, int tiles_per_wg) {
+__global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, int tiles_per_wg, int tile_lo,
+                                                                 int tile_hi) {
     constexpr int WP = WM & 3;  // weight placement
     constexpr bool WL = WP == kWeightsLds, WSLAB = WP == kWeightsLdsBySlab || WP == kWeightsLdsByRow;
     constexpr bool STREAM = (WM & kHaloStream) != 0;
@@ -406,14 +407,15 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const int tiles_x = (a.out_w + kLdsTW - 1) / kLdsTW, tiles_y = (a.out_h + TH - 1) / TH;
-    const int n_tiles = a.n * tiles_x * tiles_y;
+    // This launch covers tiles [tile_lo, tile_hi) of the a.n * tiles_x *
+    // tiles_y tiles (all of them, or one part of a convolution run in parts).
     // Workgroups are dispatched round-robin over the 8 XCDs; when the grid is
     // a multiple of 8, XCD x gets the x-th eighth of the workgroup indices, so
     // neighbouring runs of tiles share an L2.
     int g = blockIdx.x;
     if ((gridDim.x & 7) == 0) g = (g & 7) * (gridDim.x >> 3) + (g >> 3);
-    const int t_begin = g * tiles_per_wg;
-    const int t_end = min(n_tiles, t_begin + tiles_per_wg);
+    const int t_begin = tile_lo + g * tiles_per_wg;
+    const int t_end = min(tile_hi, t_begin + tiles_per_wg);
     if (t_begin >= t_end) return;  // uniform over the workgroup
     const int n_blk = blockIdx.y * (16 * NT);
     const unsigned short *wt = static_cast<const unsigned short *>(a.w);
@@ -951,7 +953,7 @@ int validate_igemm(const gt_problem &p, const gt_conv_config &) {
 }
 
 int launch_igemm(const gt_problem &p, const gt_conv_config &, const void *in, const void *w, void *out,
-                 hipStream_t s) {
+                 hipStream_t s, int part, int n_parts) {
     if ((((uintptr_t)in) | ((uintptr_t)w)) & 15)
         return set_error(GT_E_INVAL, "igemm: input and weights must be 16-byte aligned");
     IgemmArgs a;
@@ -971,7 +973,12 @@ int launch_igemm(const gt_problem &p, const gt_conv_config &, const void *in, co
     void *args[] = {&a};
     if (p.kind == GT_IGEMM_BF16_MFMA && p.filt_h == p.filt_w && ((uintptr_t)out & 15) == 0) {
         if (const LdsEntry *e = lds_kernel_for(p.filt_h, p.c_in, p.c_out)) {
-            const int64_t tiles = (int64_t)p.n * ((p.out_h + e->th - 1) / e->th) * ((p.out_w + kLdsTW - 1) / kLdsTW);
+            const int64_t all_tiles = (int64_t)p.n * ((p.out_h + e->th - 1) / e->th) * ((p.out_w + kLdsTW - 1) / kLdsTW);
+            if (all_tiles >= ((int64_t)1 << 31)) return set_error(GT_E_INVAL, "igemm: too many tiles");
+            // part k of n: tiles [all * k / n, all * (k + 1) / n)
+            const int64_t tile_lo = all_tiles * part / n_parts, tile_hi = all_tiles * (part + 1) / n_parts;
+            const int64_t tiles = tile_hi - tile_lo;
+            if (tiles == 0) return GT_OK;  // more parts than tiles: this one is empty
             const int gy = p.c_out / (16 * e->nt);
             const size_t idx = (size_t)(e - kLdsTable);
             int occ = g_lds_occupancy[idx].load(std::memory_order_relaxed);
@@ -992,13 +999,16 @@ int launch_igemm(const gt_problem &p, const gt_conv_config &, const void *in, co
             if (gx >= 8) gx = (gx + 7) / 8 * 8;
             if (per > INT32_MAX || gx * per >= ((int64_t)1 << 31))
                 return set_error(GT_E_INVAL, "igemm: too many tiles");
-            int tiles_per_wg = (int)per;
-            void *largs[] = {&a, &tiles_per_wg};
+            int tiles_per_wg = (int)per, lo = (int)tile_lo, hi = (int)tile_hi;
+            void *largs[] = {&a, &tiles_per_wg, &lo, &hi};
             dim3 grid((unsigned)gx, (unsigned)gy);
             GT_HIP_CHECK(hipLaunchKernel(e->fn, grid, dim3(e->threads), largs, (size_t)e->lds, s));
             return GT_OK;
         }
     }
+    if (n_parts != 1)
+        return set_error(GT_E_UNSUPPORTED, "igemm: a run in parts needs the LDS-staged BF16 kernel (square "
+                         "filter, instantiated filter size and channels, 16-byte aligned output)");
     if (p.kind == GT_IGEMM_BF16_MFMA) {
         const int nt = (p.c_out % 64 == 0) ? 4 : 2;
         const int per_wg = kMfmaWaves * kMT * 16;

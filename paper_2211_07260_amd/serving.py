@@ -86,16 +86,35 @@ class Step:
         self.reqs, self.event, self.batches = reqs, event, batches
 
 
+class LongJob:
+    """A long BF16 request computed as n_parts launches (conv2d_run_part)."""
+    __slots__ = ("req", "problem", "n_parts", "next_part")
+
+    def __init__(self, req, problem, n_parts):
+        self.req, self.problem, self.n_parts, self.next_part = req, problem, n_parts, 0
+
+
 class Engine:
+    """Continuous batching over streams.  Short requests are admitted in
+    groups and launched as one step per group on the short streams in turn;
+    a BF16 request of more than part_flops runs on its own stream in parts
+    of about part_flops each, at most parts_ahead of them queued, so that
+    short work issued meanwhile starts after the running part instead of
+    after the whole request (part_flops=None: no parts)."""
+
     def __init__(self, mem_budget=32 << 30, max_slots=512, max_batch=256, n_streams=2, store=None,
-                 keep_outputs=False, device="cuda:0", streams=None):
+                 keep_outputs=False, device="cuda:0", streams=None, long_stream=None, part_flops=1.0e12,
+                 parts_ahead=2):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.mem_budget, self.max_slots, self.max_batch = mem_budget, max_slots, max_batch
         # torch's caching allocator keeps freed blocks per stream: engines
-        # that share streams (streams=...) reuse each other's device buffers
+        # that share streams (streams=..., long_stream=...) reuse each
+        # other's device buffers
         self.streams = list(streams) if streams else [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
+        self.long_stream = long_stream if long_stream is not None else torch.cuda.Stream(device=self.device)
+        self.part_flops, self.parts_ahead = part_flops, max(1, parts_ahead)
         self.store = store if store is not None else autotune.load()
         self.keep_outputs = keep_outputs
         self.outputs = {}
@@ -103,6 +122,39 @@ class Engine:
         self.peak_mem = 0
         self.slots_used = 0
         self.rejected = []
+
+    def is_long(self, r):
+        return self.part_flops is not None and r.kind == "conv_bf16" and r.flops() > self.part_flops
+
+    def _start_long(self, r):
+        with self.torch.cuda.stream(self.long_stream):
+            r.bufs = make_payload(r, self.device)
+        r.config = (64, 1, 1, 1, 0, 0)
+        p = gt.conv_problem(gt.IGEMM_BF16_MFMA, 1, r.side, r.side, r.c, r.c, r.f, r.f)
+        return LongJob(r, p, max(1, int(math.ceil(r.flops() / self.part_flops))))
+
+    def _pump_long(self, jobs, events):
+        """Retire finished parts (in launch order: one stream) and keep up to
+        parts_ahead parts queued.  Returns the requests that completed."""
+        finished = []
+        while events and events[0][0].query():
+            _, job, last = events.popleft()
+            if last:
+                finished.append(job.req)
+        while len(events) < self.parts_ahead:
+            job = next((j for j in jobs if j.next_part < j.n_parts), None)
+            if job is None:
+                break
+            img, w, out = job.req.bufs
+            gt.conv2d_run_part(job.problem, job.req.config, job.next_part, job.n_parts, img, w, out,
+                               stream=self.long_stream)
+            ev = self.torch.cuda.Event()
+            ev.record(self.long_stream)
+            job.next_part += 1
+            events.append((ev, job, job.next_part == job.n_parts))
+        for r in finished:
+            jobs.remove(next(j for j in jobs if j.req is r))
+        return finished
 
     def _launch(self, reqs, stream):
         torch = self.torch
@@ -141,10 +193,11 @@ class Engine:
         # launched steps per stream: a stream runs its steps in order, so only
         # the head of each queue needs polling
         inflight = [collections.deque() for _ in self.streams]
+        long_jobs, long_events = [], collections.deque()
         done = []
         k = 0
         t0 = time.perf_counter()
-        while pending or waiting or any(inflight):
+        while pending or waiting or any(inflight) or long_jobs:
             now = time.perf_counter() - t0
             while pending and (not realtime or pending[0].t_arrive <= now):
                 waiting.append(pending.popleft())
@@ -155,6 +208,10 @@ class Engine:
             for q in inflight:
                 while q and q[0].event.query():
                     finished.append(q.popleft())
+            if long_jobs:
+                done_long = self._pump_long(long_jobs, long_events)
+                if done_long:
+                    finished.append(Step(done_long, None, []))
             for st in finished:
                 t = time.perf_counter() - t0
                 for r in st.reqs:
@@ -178,11 +235,18 @@ class Engine:
                     self.mem_used += r.bytes
                     self.slots_used += 1
                 self.peak_mem = max(self.peak_mem, self.mem_used)
-                si = k % len(self.streams)
-                inflight[si].append(self._launch(reqs, self.streams[si]))
-                k += 1
+                short = [r for r in reqs if not self.is_long(r)]
+                for r in reqs:
+                    if self.is_long(r):
+                        long_jobs.append(self._start_long(r))
+                if long_jobs:
+                    self._pump_long(long_jobs, long_events)
+                if short:
+                    si = k % len(self.streams)
+                    inflight[si].append(self._launch(short, self.streams[si]))
+                    k += 1
                 continue
-            if not any(inflight) and not waiting and pending and realtime:
+            if not any(inflight) and not long_jobs and not waiting and pending and realtime:
                 time.sleep(max(0.0, min(pending[0].t_arrive - (time.perf_counter() - t0), 1e-3)))
             else:
                 time.sleep(poll_s)
@@ -238,9 +302,11 @@ def benchmark(n_req=2000, seed=0, util=0.7, mem_budget=64 << 30, progress=print)
     # first (untimed) pass serves the timed ones: a serving process keeps its
     # device buffers, and first-time device allocation is not request work
     streams = [torch.cuda.Stream() for _ in range(2)]
-    Engine(mem_budget=mem_budget, streams=streams).run(requests_from_mix(mix), realtime=False)
+    long_stream = torch.cuda.Stream()
+    Engine(mem_budget=mem_budget, streams=streams, long_stream=long_stream).run(requests_from_mix(mix),
+                                                                              realtime=False)
     # saturation
-    eng = Engine(mem_budget=mem_budget, streams=streams)
+    eng = Engine(mem_budget=mem_budget, streams=streams, long_stream=long_stream)
     reqs = requests_from_mix(mix)
     t0 = time.perf_counter()
     done = eng.run(reqs, realtime=False)
@@ -249,7 +315,7 @@ def benchmark(n_req=2000, seed=0, util=0.7, mem_budget=64 << 30, progress=print)
     progress("saturation: %d requests in %.3f s (%.1f req/s)" % (len(done), t_sat, mu))
     lam = util * mu
     reqs = requests_from_mix(mix, rate_scale=1.0 / lam)
-    eng = Engine(mem_budget=mem_budget, streams=streams)
+    eng = Engine(mem_budget=mem_budget, streams=streams, long_stream=long_stream)
     gt.sampler_start(2.0)
     t_start = gt.sensor_read()["t_s"]
     t0 = time.perf_counter()

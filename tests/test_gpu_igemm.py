@@ -139,3 +139,45 @@ def test_igemm_unsupported(gt):
     with pytest.raises(gt.GreentuneError) as e:
         run(gt, 2, x, wt, 1)
     assert e.value.code == gt.GT_E_UNSUPPORTED
+
+
+PART_CASES = [  # n, h, w, c_in, c_out, f: several tiles, ragged rows and strips
+    (2, 40, 70, 64, 64, 3), (1, 33, 130, 32, 32, 17), (3, 20, 66, 64, 32, 5), (1, 8, 9, 64, 128, 7)]
+
+
+@pytest.mark.parametrize("case", PART_CASES)
+@pytest.mark.parametrize("n_parts", [1, 2, 3, 7, 1000])
+def test_parts_equal_the_whole_run(gt, case, n_parts):
+    # every part once, in reverse order: bit-identical to one conv2d_run, and
+    # more parts than tiles leaves some parts empty
+    n, h, w, ci, co, f = case
+    x, wt = conv_inputs(n, h, w, ci, co, f, f, seed=sum(case) + n_parts)
+    dev = torch.device("cuda:0")
+    dx, dw = x.to(dev).contiguous(), wt.to(dev).contiguous()
+    pad = (f - 1) // 2
+    p = gt.conv_problem(gt.IGEMM_BF16_MFMA, n, h, w, ci, co, f, f)
+    whole = torch.empty(n, h, w, co, dtype=torch.float32, device=dev)
+    gt.conv2d_run(p, (64, 1, 1, 1, 0, 0), dx, dw, whole)
+    parts = torch.full_like(whole, float("nan"))
+    print("case:", case, "parts:", n_parts, flush=True)
+    for k in reversed(range(n_parts)):
+        gt.conv2d_run_part(p, (64, 1, 1, 1, 0, 0), k, n_parts, dx, dw, parts)
+    torch.cuda.synchronize()
+    assert torch.equal(parts, whole)
+    ref = oracle.conv_nhwc(x.float().numpy(), wt.float().numpy(), pad, pad)
+    assert oracle.max_rel_err(parts.cpu().numpy(), ref) <= TOL[1]
+
+
+def test_parts_argument_errors(gt):
+    x, wt = conv_inputs(1, 8, 8, 64, 64, 3, 3, seed=3)
+    dev = torch.device("cuda:0")
+    out = torch.empty(1, 8, 8, 64, dtype=torch.float32, device=dev)
+    p = gt.conv_problem(gt.IGEMM_BF16_MFMA, 1, 8, 8, 64, 64, 3, 3)
+    for part, n_parts in ((2, 2), (-1, 3), (0, 0)):
+        with pytest.raises(gt.GreentuneError) as e:
+            gt.conv2d_run_part(p, (64, 1, 1, 1, 0, 0), part, n_parts, x.to(dev), wt.to(dev), out)
+        assert e.value.code == gt.GT_E_INVAL
+    pf = gt.conv_problem(gt.IGEMM_F32_VALU, 1, 8, 8, 64, 64, 3, 3)
+    with pytest.raises(gt.GreentuneError) as e:
+        gt.conv2d_run_part(pf, (64, 1, 1, 1, 0, 0), 0, 2, x.float().to(dev), wt.float().to(dev), out)
+    assert e.value.code == gt.GT_E_UNSUPPORTED

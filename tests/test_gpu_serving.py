@@ -28,9 +28,14 @@ def small_mix(n, seed):
     return serving, serving.requests_from_mix(mix)
 
 
-def test_alone_equals_mix(gt):
+@pytest.mark.parametrize("part_flops", [None, 2e8])
+def test_alone_equals_mix(gt, part_flops):
+    # part_flops=2e8 runs most BF16 requests of this mix in parts on the long
+    # stream, interleaved with the short steps
     serving, reqs = small_mix(48, seed=7)
-    eng = serving.Engine(mem_budget=1 << 30, max_batch=16, keep_outputs=True)
+    eng = serving.Engine(mem_budget=1 << 30, max_batch=16, keep_outputs=True, part_flops=part_flops)
+    n_long = sum(eng.is_long(r) for r in reqs)
+    assert (n_long == 0) == (part_flops is None)
     done = eng.run(reqs, realtime=True)
     assert len(done) == len(reqs)
     dev = torch.device("cuda:0")
