@@ -133,14 +133,19 @@ class Engine:
         p = gt.conv_problem(gt.IGEMM_BF16_MFMA, 1, r.side, r.side, r.c, r.c, r.f, r.f)
         return LongJob(r, p, max(1, int(math.ceil(r.flops() / self.part_flops))))
 
-    def _pump_long(self, jobs, events):
-        """Retire finished parts (in launch order: one stream) and keep up to
-        parts_ahead parts queued.  Returns the requests that completed."""
+    def _retire_long(self, jobs, events):
+        """Retire finished parts (in launch order: one stream); returns the
+        requests whose last part has finished (their jobs leave `jobs`)."""
         finished = []
         while events and events[0][0].query():
             _, job, last = events.popleft()
             if last:
                 finished.append(job.req)
+                jobs.remove(job)
+        return finished
+
+    def _issue_long(self, jobs, events):
+        """Keep up to parts_ahead parts queued on the long stream."""
         while len(events) < self.parts_ahead:
             job = next((j for j in jobs if j.next_part < j.n_parts), None)
             if job is None:
@@ -152,9 +157,6 @@ class Engine:
             ev.record(self.long_stream)
             job.next_part += 1
             events.append((ev, job, job.next_part == job.n_parts))
-        for r in finished:
-            jobs.remove(next(j for j in jobs if j.req is r))
-        return finished
 
     def _launch(self, reqs, stream):
         torch = self.torch
@@ -209,9 +211,10 @@ class Engine:
                 while q and q[0].event.query():
                     finished.append(q.popleft())
             if long_jobs:
-                done_long = self._pump_long(long_jobs, long_events)
+                done_long = self._retire_long(long_jobs, long_events)
                 if done_long:
                     finished.append(Step(done_long, None, []))
+                self._issue_long(long_jobs, long_events)
             for st in finished:
                 t = time.perf_counter() - t0
                 for r in st.reqs:
@@ -239,8 +242,7 @@ class Engine:
                 for r in reqs:
                     if self.is_long(r):
                         long_jobs.append(self._start_long(r))
-                if long_jobs:
-                    self._pump_long(long_jobs, long_events)
+                self._issue_long(long_jobs, long_events)
                 if short:
                     si = k % len(self.streams)
                     inflight[si].append(self._launch(short, self.streams[si]))
@@ -311,6 +313,8 @@ def benchmark(n_req=2000, seed=0, util=0.7, mem_budget=64 << 30, progress=print)
     t0 = time.perf_counter()
     done = eng.run(reqs, realtime=False)
     t_sat = time.perf_counter() - t0
+    if len(done) + len(eng.rejected) != len(reqs):
+        raise RuntimeError("serving: %d of %d requests finished" % (len(done), len(reqs)))
     mu = len(done) / t_sat
     progress("saturation: %d requests in %.3f s (%.1f req/s)" % (len(done), t_sat, mu))
     lam = util * mu
@@ -321,6 +325,8 @@ def benchmark(n_req=2000, seed=0, util=0.7, mem_budget=64 << 30, progress=print)
     t0 = time.perf_counter()
     done = eng.run(reqs, realtime=True)
     wall = time.perf_counter() - t0
+    if len(done) + len(eng.rejected) != len(reqs):
+        raise RuntimeError("serving: %d of %d requests finished" % (len(done), len(reqs)))
     t_stop = gt.sensor_read()["t_s"]
     samples = gt.sampler_stop()
     torch.cuda.synchronize()

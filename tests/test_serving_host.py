@@ -58,3 +58,52 @@ def test_energy_stats_counter_and_median():
     assert e["p_median_w"] == 501.0
     assert e["j_per_request"] == pytest.approx(501.0 * 2.99 / 100)
     assert e["p_counter_w"] == pytest.approx(500.0)
+
+
+class _FakeEvent:
+    """Completes after being queried `delay` times."""
+    def __init__(self, delay):
+        self.left = delay
+
+    def query(self):
+        self.left -= 1
+        return self.left < 0
+
+
+def test_long_jobs_issue_in_order_and_retire_once(monkeypatch):
+    # the long-request bookkeeping of the engine, without a GPU: parts are
+    # issued in job order with at most parts_ahead queued, and every request
+    # is retired exactly once, after its last part
+    from paper_2211_07260_amd import serving
+    issued = []
+    monkeypatch.setattr(serving.gt, "conv2d_run_part",
+                        lambda p, cfg, part, n, img, w, out, stream=None: issued.append((p, part, n)))
+
+    class _Torch:
+        class cuda:
+            Event = staticmethod(lambda: _Ev())
+
+    class _Ev:
+        def record(self, stream):
+            self.inner = _FakeEvent(delay=2)
+
+        def query(self):
+            return self.inner.query()
+
+    eng = object.__new__(serving.Engine)
+    eng.torch, eng.long_stream, eng.parts_ahead = _Torch, None, 2
+    reqs = [serving.Request(k, "conv_bf16", 64, 3, 32, 0.0, k) for k in range(4)]
+    jobs = []
+    for k, r in enumerate(reqs):
+        r.bufs, r.config = (None, None, None), (64, 1, 1, 1, 0, 0)
+        jobs.append(serving.LongJob(r, "p%d" % k, k + 1))   # 1, 2, 3, 4 parts
+    events = serving.collections.deque()
+    retired = []
+    for _ in range(200):
+        retired += eng._retire_long(jobs, events)
+        eng._issue_long(jobs, events)
+        assert len(events) <= 2
+        if not jobs:
+            break
+    assert retired == reqs and not events
+    assert issued == [("p%d" % k, part, k + 1) for k in range(4) for part in range(k + 1)]
