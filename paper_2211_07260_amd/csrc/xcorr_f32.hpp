@@ -196,7 +196,7 @@ __device__ __forceinline__ void xcorr_tile_lds(const XcorrArgs &a, int x0, int y
 
     constexpr int V = RowVec<TX>::value;
     const float *base = lds + ly * pitch + lx;
-    for (int i = 0; i < fh; ++i) {
+    auto filter_row = [&](int i) {
         float wr[FW];
 #pragma unroll
         for (int j = 0; j < FW; ++j) wr[j] = w[i * FW + j];
@@ -206,6 +206,16 @@ __device__ __forceinline__ void xcorr_tile_lds(const XcorrArgs &a, int x0, int y
             load_row_lds<RW, V>(row, base + (r + i) * pitch);
             fma_row<TX, TY, FW>(acc, r, row, wr);
         }
+    };
+    // Square filters with a small per-thread tile run the filter rows fully
+    // unrolled: the row addresses are then fixed offsets from one base, and
+    // rows shared by neighbouring output rows are read once.
+    constexpr bool UNROLL_ROWS = TX * TY * FW * FW <= 2400;
+    if (UNROLL_ROWS && fh == FW) {
+#pragma unroll
+        for (int i = 0; i < FW; ++i) filter_row(i);
+    } else {
+        for (int i = 0; i < fh; ++i) filter_row(i);
     }
     store_tile<TX, TY>(acc, a.out, a.out_h, a.out_w, y0 + ly, x0 + lx,
                        a.out_vec_ok && x0 + bx * TX <= a.out_w && y0 + by * TY <= a.out_h);
