@@ -119,7 +119,7 @@ struct XcorrArgs {
 // One workgroup tile whose top-left output is (x0, y0), LDS read path.  Used
 // by the one-launch-per-convolution kernel and by the persistent batched
 // kernel, so both produce bit-identical outputs.
-template <int TX, int TY, int FW>
+template <int TX, int TY, int FW, bool UNROLL_OK = true>
 __device__ __forceinline__ void xcorr_tile_lds(const XcorrArgs &a, int x0, int y0, float *lds) {
     constexpr int RW = TX + FW - 1;  // input row segment per thread
     const int bx = blockDim.x, by = blockDim.y;
@@ -209,8 +209,10 @@ __device__ __forceinline__ void xcorr_tile_lds(const XcorrArgs &a, int x0, int y
     };
     // Square filters with a small per-thread tile run the filter rows fully
     // unrolled: the row addresses are then fixed offsets from one base, and
-    // rows shared by neighbouring output rows are read once.
-    constexpr bool UNROLL_ROWS = TX * TY * FW * FW <= 2400;
+    // rows shared by neighbouring output rows are read once.  (Not in the
+    // batched kernel: under its 1024-thread bound of 128 VGPRs the hoisted
+    // row loads spill.  The FMA order is the same either way.)
+    constexpr bool UNROLL_ROWS = UNROLL_OK && TX * TY * FW * FW <= 2400;
     if (UNROLL_ROWS && fh == FW) {
 #pragma unroll
         for (int i = 0; i < FW; ++i) filter_row(i);
