@@ -207,12 +207,17 @@ __device__ __forceinline__ void xcorr_tile_lds(const XcorrArgs &a, int x0, int y
             fma_row<TX, TY, FW>(acc, r, row, wr);
         }
     };
-    // Square filters with a small per-thread tile run the filter rows fully
-    // unrolled: the row addresses are then fixed offsets from one base, and
-    // rows shared by neighbouring output rows are read once.  (Not in the
-    // batched kernel: under its 1024-thread bound of 128 VGPRs the hoisted
-    // row loads spill.  The FMA order is the same either way.)
-    constexpr bool UNROLL_ROWS = UNROLL_OK && TX * TY * FW * FW <= 2400;
+    // Square filters with a moderate per-thread tile run the filter rows
+    // fully unrolled: the row addresses are then fixed offsets from one base,
+    // and a row shared by neighbouring output rows is read from LDS once
+    // (fh + ty - 1 row reads instead of fh * ty), which saves time and
+    // power.  Bounded by code size (tx*ty*fw^2 FMAs) and, under the
+    // 1024-thread bound of 128 VGPRs, by how many rows stay live (a row
+    // serves ty output rows: ty = 8 spills beyond small tiles).  Not in the
+    // batched kernel, where the hoisted row loads spill.  The FMA order is
+    // the same either way.
+    constexpr int FMAS = TX * TY * FW * FW;
+    constexpr bool UNROLL_ROWS = UNROLL_OK && (FMAS <= 2400 || (FMAS <= 10000 && TY <= 4));
     if (UNROLL_ROWS && fh == FW) {
 #pragma unroll
         for (int i = 0; i < FW; ++i) filter_row(i);
