@@ -214,8 +214,8 @@ __device__ __forceinline__ void xcorr_tile_lds(const XcorrArgs &a, int x0, int y
     // power.  Bounded by code size (tx*ty*fw^2 FMAs) and, under the
     // 1024-thread bound of 128 VGPRs, by how many rows stay live (a row
     // serves ty output rows: ty = 8 spills beyond small tiles).  Not in the
-    // batched kernel, where the hoisted row loads spill.  The FMA order is
-    // the same either way.
+    // batched kernel for tx < 4, where the hoisted row loads spill.  The FMA
+    // order is the same either way.
     constexpr int FMAS = TX * TY * FW * FW;
     constexpr bool UNROLL_ROWS = UNROLL_OK && (FMAS <= 2400 || (FMAS <= 10000 && TY <= 4));
     if (UNROLL_ROWS && fh == FW) {

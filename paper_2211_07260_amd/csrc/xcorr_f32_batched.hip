@@ -70,7 +70,7 @@ __global__ __launch_bounds__(1024) void xcorr_f32_batched_kernel(const BatchDesc
         a.vec_ok = d[lo].flags & 1;
         a.out_vec_ok = (d[lo].flags >> 1) & 1;
         __syncthreads();  // the previous item's LDS tile is no longer read
-        xcorr_tile_lds<TX, TY, FW, false>(a, tx * blockDim.x * TX, ty * blockDim.y * TY, lds);
+        xcorr_tile_lds<TX, TY, FW, TX % 4 == 0>(a, tx * blockDim.x * TX, ty * blockDim.y * TY, lds);
     }
 }
 
