@@ -151,8 +151,16 @@ class Engine:
             if job is None:
                 break
             img, w, out = job.req.bufs
-            gt.conv2d_run_part(job.problem, job.req.config, job.next_part, job.n_parts, img, w, out,
-                               stream=self.long_stream)
+            try:
+                gt.conv2d_run_part(job.problem, job.req.config, job.next_part, job.n_parts, img, w, out,
+                                   stream=self.long_stream)
+            except gt.GreentuneError as e:
+                # a shape the tiled kernel does not cover cannot be split: run
+                # it whole (nothing of it has been issued yet)
+                if e.code != gt.GT_E_UNSUPPORTED or job.next_part != 0:
+                    raise
+                job.n_parts = 1
+                gt.conv2d_run_part(job.problem, job.req.config, 0, 1, img, w, out, stream=self.long_stream)
             ev = self.torch.cuda.Event()
             ev.record(self.long_stream)
             job.next_part += 1

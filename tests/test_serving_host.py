@@ -107,3 +107,34 @@ def test_long_jobs_issue_in_order_and_retire_once(monkeypatch):
             break
     assert retired == reqs and not events
     assert issued == [("p%d" % k, part, k + 1) for k in range(4) for part in range(k + 1)]
+
+
+def test_long_job_that_cannot_be_split_runs_whole(monkeypatch):
+    from paper_2211_07260_amd import serving
+    calls = []
+
+    def run_part(p, cfg, part, n, img, w, out, stream=None):
+        if n > 1:
+            raise serving.gt.GreentuneError(serving.gt.GT_E_UNSUPPORTED, "no parts for this shape")
+        calls.append((part, n))
+    monkeypatch.setattr(serving.gt, "conv2d_run_part", run_part)
+
+    class _Ev:
+        def record(self, stream):
+            pass
+
+        def query(self):
+            return True
+
+    class _Torch:
+        class cuda:
+            Event = staticmethod(lambda: _Ev())
+
+    eng = object.__new__(serving.Engine)
+    eng.torch, eng.long_stream, eng.parts_ahead = _Torch, None, 2
+    r = serving.Request(0, "conv_bf16", 64, 11, 32, 0.0, 0)
+    r.bufs, r.config = (None, None, None), (64, 1, 1, 1, 0, 0)
+    jobs, events = [serving.LongJob(r, "p", 5)], serving.collections.deque()
+    eng._issue_long(jobs, events)
+    assert calls == [(0, 1)] and len(events) == 1 and jobs[0].n_parts == 1
+    assert eng._retire_long(jobs, events) == [r] and not jobs
