@@ -136,11 +136,24 @@ def test_large_lds_tile(gt):
     assert oracle.max_rel_err(got, ref) <= TOL
 
 
+def _tuned_configs():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2211_07260_amd",
+                        "tuned", "xcorr_f32_4096x4096_f17.json")
+    with open(path) as fh:
+        t = json.load(fh)
+    return [tuple(t["time_optimal"]["config"]), tuple(t["energy_optimal"]["config"])]
+
+
 def test_full_size_4096(gt):
-    # the benchmark workload: 4096x4096 output, 17x17 filter, whole output vs the oracle
+    # the benchmark workload: 4096x4096 output, 17x17 filter, whole output vs
+    # the oracle, in the launch configurations the bench times (the stored
+    # time- and energy-optimal configs) and a few others (looped rows, direct
+    # read path)
     img, w = xcorr_inputs(4096, 4096, 17, 17, seed=0)
     ref = oracle.xcorr2d(img.numpy(), w.numpy())
-    for cfg in [(32, 8, 4, 4, 0, 0), (64, 4, 8, 4, 1, 0), (32, 8, 4, 8, 0, 1)]:
+    for cfg in _tuned_configs() + [(32, 8, 4, 8, 0, 0), (64, 4, 8, 4, 1, 0), (32, 8, 4, 8, 0, 1)]:
         print("case: 4096 cfg=%s" % (cfg,), flush=True)
         got = _run(gt, img, w, cfg, 4096, 4096).numpy()
         err = oracle.max_rel_err(got, ref)
