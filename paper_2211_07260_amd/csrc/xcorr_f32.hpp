@@ -212,12 +212,13 @@ __device__ __forceinline__ void xcorr_tile_lds(const XcorrArgs &a, int x0, int y
     // and a row shared by neighbouring output rows is read from LDS once
     // (fh + ty - 1 row reads instead of fh * ty), which saves time and
     // power.  Bounded by code size (tx*ty*fw^2 FMAs) and, under the
-    // 1024-thread bound of 128 VGPRs, by how many rows stay live (a row
-    // serves ty output rows: ty = 8 spills beyond small tiles).  Not in the
+    // 1024-thread bound of 128 VGPRs, by the rows a thread keeps live: a row
+    // serves ty output rows, so up to ty rows of tx + fw - 1 values (the one
+    // tile past that bound, 4 x 8 at 17x17, spills when unrolled).  Not in the
     // batched kernel for tx < 4, where the hoisted row loads spill.  The FMA
     // order is the same either way.
     constexpr int FMAS = TX * TY * FW * FW;
-    constexpr bool UNROLL_ROWS = UNROLL_OK && (FMAS <= 2400 || (FMAS <= 10000 && TY <= 4));
+    constexpr bool UNROLL_ROWS = UNROLL_OK && (FMAS <= 2400 || (FMAS <= 10000 && TY * (TX + FW - 1) <= 128));
     if (UNROLL_ROWS && fh == FW) {
 #pragma unroll
         for (int i = 0; i < FW; ++i) filter_row(i);
