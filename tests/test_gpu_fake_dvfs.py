@@ -242,3 +242,20 @@ def test_dvfs_state_file_and_recovery(gt, tmp_path, monkeypatch):
     files[0].unlink()
     gt.init(0, gt.INIT_ALLOW_DVFS)
     gt.shutdown()
+
+
+def test_measure_load_argument_errors(gt):
+    gt.init(0, 0)
+    try:
+        dev = torch.device("cuda:0")
+        small = torch.empty(1 << 18, dtype=torch.float32, device=dev)   # 1 MiB
+        for kind in (gt.LOAD_FP32_FMA, gt.LOAD_COPY):
+            with pytest.raises(gt.GreentuneError) as e:
+                gt.measure_load(kind, small, window_s=0.05, discard_s=0.01)
+            assert e.value.code == gt.GT_E_INVAL
+        buf = torch.empty(1 << 22, dtype=torch.float32, device=dev)
+        with pytest.raises(gt.GreentuneError) as e:
+            gt.measure_load(7, buf, window_s=0.05, discard_s=0.01)
+        assert e.value.code == gt.GT_E_INVAL
+    finally:
+        gt.shutdown()

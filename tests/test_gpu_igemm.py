@@ -181,3 +181,22 @@ def test_parts_argument_errors(gt):
     with pytest.raises(gt.GreentuneError) as e:
         gt.conv2d_run_part(pf, (64, 1, 1, 1, 0, 0), 0, 2, x.float().to(dev), wt.float().to(dev), out)
     assert e.value.code == gt.GT_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("f", [3, 5])
+def test_parts_full_size(gt, f):
+    # the benchmark's multi-channel workload (N=16, 128x128, C=64) in 7 parts on
+    # two streams: bit-identical to the whole run
+    x, wt = conv_inputs(16, 128, 128, 64, 64, f, f, seed=0)
+    dev = torch.device("cuda:0")
+    dx, dw = x.to(dev).contiguous(), wt.to(dev).contiguous()
+    p = gt.conv_problem(gt.IGEMM_BF16_MFMA, 16, 128, 128, 64, 64, f, f)
+    whole = torch.empty(16, 128, 128, 64, dtype=torch.float32, device=dev)
+    gt.conv2d_run(p, (64, 1, 1, 1, 0, 0), dx, dw, whole)
+    parts = torch.full_like(whole, float("nan"))
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    for k in range(7):
+        gt.conv2d_run_part(p, (64, 1, 1, 1, 0, 0), k, 7, dx, dw, parts, stream=streams[k % 2])
+    torch.cuda.synchronize()
+    assert torch.equal(parts, whole)
