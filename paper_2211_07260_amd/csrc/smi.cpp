@@ -339,8 +339,11 @@ int dvfs_apply(const gt_clock &clk) {
     // leaves a record for the next gt_init to restore from
     if (!write_state_file(clk)) return set_error(GT_E_PERM, "DVFS: cannot write %s", dvfs_state_path().c_str());
     const int rc = g_backend.apply(g_backend.user, st.dev.ordinal, clk.kind, clk.value);
-    if (rc != 0) return set_error(GT_E_PERM, "DVFS: the backend refused %s = %d (status %d)",
-                                  clk.kind == GT_CLOCK_SCLK_MHZ ? "clock limit" : "power cap", clk.value, rc);
+    if (rc != 0) {
+        if (!g_backend_changed) unlink(dvfs_state_path().c_str());  // nothing of ours is in force
+        return set_error(GT_E_PERM, "DVFS: the backend refused %s = %d (status %d)",
+                         clk.kind == GT_CLOCK_SCLK_MHZ ? "clock limit" : "power cap", clk.value, rc);
+    }
     g_backend_changed = true;
     st.clock = clk;
     return GT_OK;

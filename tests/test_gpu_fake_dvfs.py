@@ -259,3 +259,19 @@ def test_measure_load_argument_errors(gt):
         assert e.value.code == gt.GT_E_INVAL
     finally:
         gt.shutdown()
+
+
+def test_refused_first_knob_change_leaves_no_state_file(gt, tmp_path, monkeypatch):
+    monkeypatch.setenv("TMPDIR", str(tmp_path))
+    gt.set_dvfs_backend(lambda dev, kind, value: 5, lambda dev: 0)   # apply always refuses
+    try:
+        gt.init(0, gt.INIT_ALLOW_DVFS)
+        buf = torch.empty(1 << 22, dtype=torch.float32, device=torch.device("cuda:0"))
+        with pytest.raises(gt.GreentuneError) as e:
+            gt.measure_load(gt.LOAD_COPY, buf, gt.clock(gt.CLOCK_SCLK_MHZ, 1500), window_s=0.05, discard_s=0.01)
+        assert e.value.code == gt.GT_E_PERM
+        assert not list(tmp_path.glob("greentune-dvfs-*.state"))
+        assert gt.dvfs_state() == (False, (0, 0))
+    finally:
+        gt.shutdown()
+        gt.set_dvfs_backend(None)
