@@ -48,8 +48,24 @@ def cpu_baseline(img, w, min_seconds=8.0):
         el = time.perf_counter() - t0
         if el >= min_seconds:
             break
-    return {"value": flops * reps / el / 1e9, "unit": "GFLOP/s", "cores": nthreads, "kind": "oracle",
-            "sample": "full 4096x4096x17x17 FP64 cross-correlation x%d (%.1f s wall)" % (reps, el)}
+    res = {"value": flops * reps / el / 1e9, "unit": "GFLOP/s", "cores": nthreads, "kind": "oracle",
+           "sample": "full 4096x4096x17x17 FP64 cross-correlation x%d (%.1f s wall)" % (reps, el)}
+    # one core on the first 512 output rows, and the multi-channel oracle on
+    # one image of the N=16, 128x128, C=64 workload (3x3 and 5x5)
+    t0 = time.perf_counter()
+    oracle.xcorr2d(a[:512 + 16, :], b, nthreads=1)
+    res["single_thread_gflops"] = 2.0 * 512 * 4096 * 289 / (time.perf_counter() - t0) / 1e9
+    from synthetic import conv_inputs
+    mc = {}
+    for f in (3, 5):
+        x, wt = conv_inputs(1, 128, 128, 64, 64, f, f, seed=0)
+        xf, wf = x.float().numpy(), wt.float().numpy()
+        t0 = time.perf_counter()
+        oracle.conv_nhwc(xf, wf, (f - 1) // 2, (f - 1) // 2, nthreads=nthreads)
+        mc["f%d" % f] = 2.0 * 128 * 128 * 64 * 64 * f * f / (time.perf_counter() - t0) / 1e9
+    res["multichannel_gflops"] = mc
+    res["extra_samples"] = "single thread: 512 of the 4096 output rows; multi-channel: 1 of the 16 images"
+    return res
 
 
 def igemm_extras(gt, torch, dev, steps=20, energy=True):
