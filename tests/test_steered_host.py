@@ -1,6 +1,6 @@
 """Model-steered clock search (section V.D-E) end to end on a simulated
 device (CPU): power follows Eq. 2/3 plus noise, run time scales as 1/f.  The
-library fits the model to 5 readings, picks the band, and the driver measures
+library fits the model to 5 readings, picks the band, and the search loop measures
 only band clocks; the result must match the exhaustive clock sweep's energy
 optimum closely while measuring at least 5x fewer clock points."""
 import numpy as np
