@@ -221,11 +221,14 @@ double gt_power_model_eval(const gt_power_model *model, double f_mhz);
 /* Throttling clock: where the unclipped model p_idle + alpha f v(f)^2 reaches
  * p_max (bisection); +inf if it never does below 1e7 MHz. */
 double gt_power_model_throttle_clock(const gt_power_model *model);
-/* Model-optimal clock: argmin over settable[0..n) of the energy estimate of
- * section V.D, P*(f)/f, with performance linear in the clock only up to the
- * throttling clock (Fig. 8): E*(f) = P*(f_e)/f_e, f_e = min(f, f_thr).  Ties
- * (relative gap <= 1e-12) go to the higher clock.  Then the band: the settable clocks within [(1-rel_half) f_opt,
- * (1+rel_half) f_opt], ascending (rel_half = 0.1 in the paper).
+/* Model-optimal clock: argmin of the energy estimate of section V.D,
+ * P*(f)/f, over the settable clocks the device can hold, settable[i] <= f_thr
+ * (the paper takes performance as linear in the clock, and fits and searches,
+ * only up to where throttling starts: Fig. 8 and section V.D); the lowest
+ * settable clock when every one lies above f_thr.  Ties (relative gap
+ * <= 1e-12) go to the higher clock.  Then the band: the settable clocks
+ * within [(1-rel_half) f_opt, (1+rel_half) f_opt], ascending (rel_half = 0.1
+ * in the paper).
  * GT_E_CAPACITY if cap is too small (*n_band still written). */
 int gt_power_model_band(const gt_power_model *model, const double *settable, size_t n,
                         double rel_half, double *f_opt, double *band, size_t cap, size_t *n_band);

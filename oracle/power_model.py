@@ -18,12 +18,15 @@ below tau and grows with slope beta above it:
 ``literal=True`` evaluates the printed form instead.
 
 Energy per run is estimated as E*(f) proportional to P*(f)/f (absolute
-power divided by clock frequency, run time scaling as 1/f), with the clock
-capped at the throttling point where the model reaches P_max (the paper
-estimates performance as linear in the clock up to where throttling occurs);
-the model-optimal clock is its argmin over the settable clocks,
-ties going to the highest clock (faster at equal energy); the tuning band is
-the settable clocks within +-10 % of that optimum.
+power divided by clock frequency, run time scaling as 1/f).  The paper takes
+performance as linear in the clock, and fits and searches the clock range,
+only up to the clock where throttling starts (Fig. 8 and the model-fitting
+passage of section V.D); above the throttling clock f_thr, where the model
+reaches P_max, the device cannot hold the requested clock.  So the
+model-optimal clock is the argmin of P*(f)/f over the settable clocks at or
+below f_thr (the lowest settable clock when none is), ties going to the
+highest such clock (faster at equal energy); the tuning band is the settable
+clocks within +-10 % of that optimum.
 
 The fit is the non-linear least-squares problem the paper solves with
 Levenberg-Marquardt.  The oracle solves it by exhaustive variable projection
@@ -83,15 +86,20 @@ def energy_estimate(f, model, f_thr=None):
     f = np.asarray(f, dtype=np.float64)
     f_eff = np.minimum(f, throttle_clock(model) if f_thr is None else f_thr)
     return power(f_eff, model["p_idle"], model["alpha"], model["beta"], model["tau"],
-                 model["p_max"]) / f_eff
+                 model["p_max"], literal=model.get("literal", False)) / f_eff
 
 
 def optimal_clock(settable, model):
-    """argmin over the settable clocks of E*(f); ties -> highest clock."""
-    best_f, best_e = None, None
+    """argmin of E*(f) = P*(f)/f over the settable clocks f <= f_thr (the
+    clocks the device can hold); ties -> the highest such clock.  When every
+    settable clock lies above f_thr the lowest one is returned."""
+    s = sorted(float(x) for x in settable)
     f_thr = throttle_clock(model)
-    for f in sorted(float(x) for x in settable):
-        e = float(energy_estimate(f, model, f_thr))
+    held = [f for f in s if f <= f_thr] or s[:1]
+    best_f, best_e = None, None
+    for f in held:
+        e = float(power(f, model["p_idle"], model["alpha"], model["beta"], model["tau"], model["p_max"],
+                        literal=model.get("literal", False))) / f
         if best_e is None or e <= best_e * (1.0 + TIE_REL):
             if best_e is None or e < best_e:
                 best_e = e
@@ -113,8 +121,10 @@ def sse(params, f, p, p_max, literal=False):
 
 
 def _linear_given(f, p, p_max, beta, tau, literal):
-    """For fixed (beta, tau): least squares for (P_idle, alpha) over the points
-    whose unclipped model stays below P_max, then clamp to P_idle, alpha >= 0."""
+    """For fixed (beta, tau): linear least squares for (P_idle, alpha) over all
+    the points, treating the model as unclipped, then clamp to P_idle,
+    alpha >= 0.  This only seeds the grid search and the Levenberg-Marquardt
+    polish below, which minimise the clipped residual."""
     g = f * voltage(f, beta, tau, literal) ** 2
     a = np.stack([np.ones_like(f), g], axis=1)
     sol, *_ = np.linalg.lstsq(a, p, rcond=None)

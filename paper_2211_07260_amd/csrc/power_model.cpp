@@ -314,16 +314,18 @@ int gt_power_model_band(const gt_power_model *m, const double *settable, size_t 
     std::vector<double> s(settable, settable + n);
     std::sort(s.begin(), s.end());
     if (!(s[0] > 0)) return set_error(GT_E_INVAL, "gt_power_model_band: clocks must be positive");
-    // energy estimate E*(f) = P*(f_e)/f_e with f_e = min(f, throttling clock):
-    // above the throttling clock the device runs at that clock and P_max.
-    // Ascending scan so ties end on the higher clock.
+    // energy estimate E*(f) = P*(f)/f over the clocks the device can hold:
+    // the paper fits and searches only up to where throttling starts, and
+    // above the throttling clock the requested clock is not reached.  When
+    // every settable clock lies above it, the lowest one.  Ascending scan so
+    // ties end on the highest held clock.
     const double f_thr = gt_power_model_throttle_clock(m);
-    auto energy = [&](double f) {
-        const double fe = std::min(f, f_thr);
-        return gt_power_model_eval(m, fe) / fe;
-    };
+    size_t n_held = 0;
+    while (n_held < n && s[n_held] <= f_thr) ++n_held;
+    if (n_held == 0) n_held = 1;
+    auto energy = [&](double f) { return gt_power_model_eval(m, f) / f; };
     double best_f = s[0], best_e = energy(s[0]);
-    for (size_t i = 1; i < n; ++i) {
+    for (size_t i = 1; i < n_held; ++i) {
         const double e = energy(s[i]);
         if (e <= best_e * (1.0 + 1e-12)) {
             if (e < best_e) best_e = e;

@@ -161,7 +161,11 @@ def test_throttle_clock_matches_oracle(m):
 
 @pytest.mark.parametrize("m", MODELS + [dict(p_idle=0.0, alpha=0.5, beta=0.01, tau=1200.0, p_max=1e9),
                                        dict(p_idle=320.0, alpha=0.37, beta=0.00115, tau=1020.0, p_max=1400.0),
-                                       dict(p_idle=300.0, alpha=0.1, beta=0.0, tau=1000.0, p_max=1e9)])
+                                       dict(p_idle=300.0, alpha=0.1, beta=0.0, tau=1000.0, p_max=1e9),
+                                       dict(p_idle=300.0, alpha=0.55, beta=5e-5, tau=1500.0, p_max=1400.0),
+                                       dict(p_idle=300.0, alpha=0.5, beta=0.0, tau=1000.0, p_max=1400.0),
+                                       dict(p_idle=300.0, alpha=0.5, beta=0.0, tau=1000.0, p_max=400.0),
+                                       dict(p_idle=250.0, alpha=0.4, beta=4e-4, tau=1600.0, p_max=1100.0)])
 @pytest.mark.parametrize("step", [100.0, 25.0, 5.0])
 def test_band_matches_oracle(m, step):
     settable = list(np.arange(500.0, 2400.0 + 1e-9, step))
@@ -170,6 +174,18 @@ def test_band_matches_oracle(m, step):
     om_ = dict(m)
     assert f_opt == opm.optimal_clock(settable, om_)
     assert band == opm.clock_band(settable, f_opt, 0.1)
+    f_thr = opm.throttle_clock(om_)
+    assert f_opt <= f_thr or f_opt == settable[0]
+
+
+def test_plateau_model_optimum_below_throttle():
+    # a full load at the socket cap: the model reaches P_max at 1918.8 MHz
+    # while P*(f)/f would still fall above it; the optimum is a held clock
+    pmod = gt.power_model(300.0, 0.55, 5e-5, 1500.0, 1400.0)
+    f_thr = gt.power_model_throttle_clock(pmod)
+    assert f_thr == pytest.approx(1918.8, abs=0.1)
+    f_opt, band = gt.power_model_band(pmod, list(np.arange(500.0, 2400.0 + 1e-9, 5.0)), 0.1)
+    assert f_opt == 1915.0 and band[0] == 1725.0 and band[-1] == 2105.0
 
 
 def _synth(f, m):

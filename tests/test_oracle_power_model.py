@@ -94,6 +94,47 @@ def test_optimum_never_above_throttle():
     assert abs(f_opt - grid[np.argmin(e)]) <= 10.0
 
 
+def test_beta_zero_with_throttling_picks_largest_held_clock():
+    # beta = 0: E*(f) = P_idle/f + alpha falls with f, but the model reaches
+    # P_max at f_thr = (P_max - P_idle)/alpha = 2200 MHz exactly; the device
+    # cannot hold a clock above it, so f* is the largest settable clock <= 2200
+    m = dict(p_idle=300.0, alpha=0.5, beta=0.0, tau=1000.0, p_max=1400.0)
+    assert pm.throttle_clock(m) == pytest.approx(2200.0, rel=1e-12)
+    assert pm.optimal_clock(np.arange(500.0, 2401.0, 25.0), m) == 2200.0
+    settable = np.arange(500.0, 2401.0, 30.0)  # ... 2180, 2210, ...
+    f_opt = pm.optimal_clock(settable, m)
+    assert f_opt == 2180.0
+    # the band is centred there: [1962, 2398]
+    assert pm.clock_band(settable, f_opt) == [f for f in settable if 1962.0 <= f <= 2398.0]
+
+
+def test_throttle_plateau_optimum_from_the_cubic():
+    # P_idle 300, alpha 0.55, beta 5e-5, tau 1500, P_max 1400 (a full load at
+    # the socket cap).  With v = a + beta f, a = 1 - beta tau, the throttling
+    # clock is the real root of the cubic
+    #   alpha beta^2 f^3 + 2 alpha a beta f^2 + alpha a^2 f + P_idle - P_max = 0
+    m = dict(p_idle=300.0, alpha=0.55, beta=5e-5, tau=1500.0, p_max=1400.0)
+    a = 1.0 - m["beta"] * m["tau"]
+    roots = np.roots([m["alpha"] * m["beta"] ** 2, 2 * m["alpha"] * a * m["beta"], m["alpha"] * a * a,
+                      m["p_idle"] - m["p_max"]])
+    f_thr = max(r.real for r in roots if abs(r.imag) < 1e-9 and r.real > m["tau"])
+    assert f_thr == pytest.approx(1918.8, abs=0.1)
+    assert pm.throttle_clock(m) == pytest.approx(f_thr, rel=1e-9)
+    # dE*/df = -P_idle/f^2 + 2 alpha beta v(f) is still negative at f_thr (its
+    # zero lies near 2290 MHz), so E* falls all the way to the throttling clock
+    assert -m["p_idle"] / f_thr ** 2 + 2 * m["alpha"] * m["beta"] * (a + m["beta"] * f_thr) < 0
+    settable = np.arange(500.0, 2401.0, 25.0)
+    f_opt = pm.optimal_clock(settable, m)
+    assert f_opt == 1900.0 and f_opt <= f_thr
+    assert pm.clock_band(settable, f_opt) == [f for f in settable if 1710.0 <= f <= 2090.0]
+
+
+def test_all_clocks_throttle_gives_lowest_clock():
+    # P_max below the power at the lowest settable clock: nothing can be held
+    m = dict(p_idle=300.0, alpha=0.5, beta=0.0, tau=1000.0, p_max=400.0)  # f_thr = 200
+    assert pm.optimal_clock(np.arange(500.0, 2401.0, 100.0), m) == 500.0
+
+
 def test_band_closed_form():
     settable = np.arange(100.0, 2401.0, 100.0)
     assert pm.clock_band(settable, 1500.0) == [1400.0, 1500.0, 1600.0]

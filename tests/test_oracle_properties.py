@@ -92,3 +92,22 @@ def test_band_brackets_the_optimum(p_idle, alpha, beta, tau, step):
     assert f_opt in band and all(0.9 * f_opt - 1e-9 <= f <= 1.1 * f_opt + 1e-9 for f in band)
     e = [opm.energy_estimate(f, m) for f in settable]
     assert opm.energy_estimate(f_opt, m) <= min(e) * (1 + 1e-12)
+
+
+@SETTINGS
+@given(st.floats(50, 400), st.floats(0.05, 1.0), st.floats(0, 5e-3), st.floats(600, 2200),
+       st.floats(500, 3000), st.sampled_from([5.0, 25.0, 100.0]))
+def test_optimum_is_a_held_clock(p_idle, alpha, beta, tau, p_max, step):
+    # f* never lies above the throttling clock while some settable clock does
+    # not, and no held clock has a lower P*(f)/f
+    m = dict(p_idle=p_idle, alpha=alpha, beta=beta, tau=tau, p_max=p_max)
+    settable = list(np.arange(500.0, 2400.0 + 1e-9, step))
+    f_thr = opm.throttle_clock(m)
+    f_opt = opm.optimal_clock(settable, m)
+    held = [f for f in settable if f <= f_thr]
+    if not held:
+        assert f_opt == settable[0]
+        return
+    assert f_opt in held
+    e = lambda f: float(opm.power(f, p_idle, alpha, beta, tau, p_max)) / f  # noqa: E731
+    assert all(e(f_opt) <= e(f) * (1 + 1e-12) for f in held)
