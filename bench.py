@@ -3,11 +3,12 @@
 Workload: single-channel FP32 cross-correlation, output 4096 x 4096, filter
 17 x 17, input 4112 x 4112, uniform[0,1) from seed 0 (synthetic).  One step =
 one launch of the kernel with the tuned configuration, inputs resident in HBM.
-The warm-up (about half a second of launches) brings the graphics clock to its
-loaded level before the timed region.
-The energy efficiency (GFLOP/s/W) of the same configuration is measured after
-the timed region with the library's measure_time_energy (median socket power
-times time per run).  Prints one JSON line.
+The warm-up launches for at least 0.5 s (and at least --warmup launches) so
+that the graphics clock has reached its loaded level before the timed region.
+The energy efficiency (GFLOP/s/W) of the time- and energy-tuned
+configurations is measured after the timed region with the library's
+measure_time_energy (median socket power times time per run).  Prints one
+JSON line.
 """
 import argparse
 import json
@@ -32,46 +33,90 @@ def load_tuned():
     return None
 
 
-def cpu_baseline(img, w, min_seconds=8.0):
-    """The FP64 oracle on the host cores over the full workload, repeated until
-    about min_seconds have passed."""
+def host_cpu():
+    """Cores this process may run on, the host's total, and the CPU model."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    model = None
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    omp = os.environ.get("OMP_NUM_THREADS")
+    threads = min(avail, int(omp)) if omp and omp.isdigit() and int(omp) > 0 else avail
+    return {"nproc": avail, "cpu_count": os.cpu_count(), "omp_num_threads": omp, "model": model,
+            "threads": threads}
+
+
+def _median_time(fn, reps=5):
+    fn()  # warm-up
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[len(ts) // 2]
+
+
+def cpu_baseline(img, w, gpu_out=None):
+    """The FP64 oracle on the host cores this process is given (the CPU
+    share of one GPU on a shared host, OMP_NUM_THREADS), median of 5 timed
+    runs after one warm-up: the full 4096x4096x17x17 workload, the small
+    256x256x17x17 one, both multi-channel ones, and the full workload's
+    first 1024 output rows on one core.  gpu_out: host copies of the GPU
+    outputs of the same workloads ({"xcorr": ..., "bf16_mfma_f3": ..., ...}),
+    whose normwise error against the oracle's results is reported under
+    "max_rel_err"."""
     import oracle
-    nthreads = min(16, os.cpu_count() or 1)
-    flops = 2.0 * 4096 * 4096 * 17 * 17
+    from synthetic import conv_inputs, xcorr_inputs
+    gpu_out = gpu_out or {}
+    errs = {}
+    cpu = host_cpu()
+    nt = cpu["threads"]
     a, b = img.numpy(), w.numpy()
-    oracle.xcorr2d(a[:64 + 16, :], b, nthreads=nthreads)  # load + warm
-    t0 = time.perf_counter()
-    reps = 0
-    while True:
-        oracle.xcorr2d(a, b, nthreads=nthreads)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= min_seconds:
-            break
-    res = {"value": flops * reps / el / 1e9, "unit": "GFLOP/s", "cores": nthreads, "kind": "oracle",
-           "sample": "full 4096x4096x17x17 FP64 cross-correlation x%d (%.1f s wall)" % (reps, el)}
-    # one core on the first 512 output rows, and the multi-channel oracle on
-    # one image of the N=16, 128x128, C=64 workload (3x3 and 5x5)
-    t0 = time.perf_counter()
-    oracle.xcorr2d(a[:512 + 16, :], b, nthreads=1)
-    res["single_thread_gflops"] = 2.0 * 512 * 4096 * 289 / (time.perf_counter() - t0) / 1e9
-    from synthetic import conv_inputs
+    ref = {}
+    t_full = _median_time(lambda: ref.__setitem__("xcorr", oracle.xcorr2d(a, b, nthreads=nt)))
+    if "xcorr" in gpu_out:
+        errs["xcorr_f32_4096_f17"] = oracle.max_rel_err(gpu_out["xcorr"], ref["xcorr"])
+    del ref["xcorr"]
+    res = {"value": 2.0 * 4096 * 4096 * 289 / t_full / 1e9, "unit": "GFLOP/s", "cores": nt, "kind": "oracle",
+           "sample": "full 4096x4096x17x17 FP64 cross-correlation, median of 5 runs (%.3f s each) on %d threads"
+                     % (t_full, nt), "host": cpu}
+    s_img, s_w = xcorr_inputs(256, 256, 17, 17, seed=0)
+    sa, sb = s_img.numpy(), s_w.numpy()
+    t_small = _median_time(lambda: oracle.xcorr2d(sa, sb, nthreads=nt))
+    res["small_256x256_f17"] = {"gflops": 2.0 * 256 * 256 * 289 / t_small / 1e9, "s": t_small}
+    t_one = _median_time(lambda: oracle.xcorr2d(a[:1024 + 16, :], b, nthreads=1))
+    res["single_thread_gflops"] = 2.0 * 1024 * 4096 * 289 / t_one / 1e9
     mc = {}
     for f in (3, 5):
-        x, wt = conv_inputs(1, 128, 128, 64, 64, f, f, seed=0)
+        x, wt = conv_inputs(16, 128, 128, 64, 64, f, f, seed=0)
         xf, wf = x.float().numpy(), wt.float().numpy()
-        t0 = time.perf_counter()
-        oracle.conv_nhwc(xf, wf, (f - 1) // 2, (f - 1) // 2, nthreads=nthreads)
-        mc["f%d" % f] = 2.0 * 128 * 128 * 64 * 64 * f * f / (time.perf_counter() - t0) / 1e9
-    res["multichannel_gflops"] = mc
-    res["extra_samples"] = "single thread: 512 of the 4096 output rows; multi-channel: 1 of the 16 images"
+        t = _median_time(lambda: ref.__setitem__("mc", oracle.conv_nhwc(xf, wf, (f - 1) // 2, (f - 1) // 2,
+                                                                         nthreads=nt)))
+        mc["f%d" % f] = {"gflops": 2.0 * 16 * 128 * 128 * 64 * 64 * f * f / t / 1e9, "s": t}
+        for name in ("bf16_mfma_f%d" % f, "f32_valu_f%d" % f):
+            if name in gpu_out:
+                errs[name] = oracle.max_rel_err(gpu_out[name], ref["mc"])
+        del ref["mc"]
+    res["multichannel_n16_c64_128x128"] = mc
+    res["max_rel_err"] = errs
+    res["extra_samples"] = "single thread: the first 1024 of the 4096 output rows; all figures median of 5"
     return res
 
 
-def igemm_extras(gt, torch, dev, steps=20, energy=True):
+def igemm_extras(gt, torch, dev, steps=20, energy=True, outputs=None):
     """Multi-channel conv (N=16, C_in=C_out=64, 128x128, same padding), BF16
     MFMA and FP32 VALU paths on the same BF16-valued data: ms, TFLOP/s and
-    (measured with measure_time_energy) GFLOP/s/W."""
+    (measured with measure_time_energy) GFLOP/s/W.  Host copies of the
+    outputs go to `outputs` (for the error against the oracle)."""
     from synthetic import conv_inputs
     res = {}
     for f in (3, 5):
@@ -99,6 +144,9 @@ def igemm_extras(gt, torch, dev, steps=20, energy=True):
                 except gt.GreentuneError as e:
                     r["energy_error"] = str(e)
             res["%s_f%d" % (name, f)] = r
+            if outputs is not None:
+                torch.cuda.synchronize()
+                outputs["%s_f%d" % (name, f)] = out.cpu().numpy()
     return res
 
 
@@ -131,7 +179,8 @@ def main():
     ap.add_argument("--probe", action="store_true", help="run the roofline probes only")
     ap.add_argument("--no-extras", action="store_true", help="skip the multi-channel timings")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-mix run")
-    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-requests", type=int, default=8000)
+    ap.add_argument("--warmup-seconds", type=float, default=0.5)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the tuning method and its kernels run on a single "
@@ -171,10 +220,19 @@ def main():
     prob = gt.xcorr_problem(4096, 4096, 17, 17)
     flops = gt.problem_flops(prob)
 
-    for _ in range(args.warmup):
-        gt.conv2d_run(prob, cfg, d_in, d_w, out)
-    torch.cuda.synchronize()
-    print("bench: warmup done, config %s (%s)" % (cfg, cfg_src), file=sys.stderr, flush=True)
+    # warm up by time: the clock ramps to its loaded level over a fraction of
+    # a second, so a launch count alone (a few launches are ~0.7 ms) times the
+    # kernel before the clock has settled
+    t_w0 = time.perf_counter()
+    n_warm = 0
+    while n_warm < args.warmup or time.perf_counter() - t_w0 < args.warmup_seconds:
+        for _ in range(50):
+            gt.conv2d_run(prob, cfg, d_in, d_w, out)
+        n_warm += 50
+        torch.cuda.synchronize()
+    warmup_s = time.perf_counter() - t_w0
+    print("bench: warmup %d launches in %.2f s, config %s (%s)" % (n_warm, warmup_s, cfg, cfg_src),
+          file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -189,6 +247,7 @@ def main():
     gflops = flops / (ms * 1e-3) / 1e9
     print("bench: timed %d steps, %.4f ms/step, %.1f GFLOP/s" % (args.steps, ms, gflops),
           file=sys.stderr, flush=True)
+    gpu_out = {"xcorr": out.cpu().numpy()} if not args.no_cpu else None
 
     energy = None
     if not args.no_energy:
@@ -225,7 +284,7 @@ def main():
 
     extras = None
     if not args.no_extras:
-        extras = igemm_extras(gt, torch, dev, energy=not args.no_energy)
+        extras = igemm_extras(gt, torch, dev, energy=not args.no_energy, outputs=gpu_out)
 
     serving_rep = None
     if not args.no_serving:
@@ -253,6 +312,8 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "warmup_s": round(warmup_s, 3),
+        "warmup_launches": n_warm,
         "ms_per_step": round(ms, 5),
         "higher_is_better": True,
         "scaling": "weak",
@@ -264,19 +325,28 @@ def main():
                    "parallelism": "single GPU"},
         "gflops_per_w": (energy or {}).get("time_tuned", {}).get("gflops_per_w"),
         "energy": energy,
-        "synthetic_loads": loads,
-        "multichannel": extras,
-        "serving": serving_rep,
         "wall_s_timed": round(t_wall, 4),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                      "frac_of_nonpacked_peak": round(achieved / FP32_NONPACKED_PEAK_TFLOPS, 4),
                      "traffic": traffic},
     }
+    result.update(synthetic_loads=loads, multichannel=extras, serving=serving_rep)
     if tuned:
-        result["tuning"] = {k: tuned[k] for k in tuned if k not in ("rows",)}
+        result["stored_sweep"] = dict(
+            source="the committed sweep of the tune space (paper_2211_07260_amd/tuned/), measured on MI355X "
+                   "before this run; not re-measured here",
+            **{k: tuned[k] for k in tuned if k not in ("rows",)})
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(img, w)
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        cb = cpu_baseline(img, w, gpu_out)
+        result["cpu_baseline"] = cb
+        errs = cb.get("max_rel_err", {})
+        # the error of each GPU result against the FP64 oracle, beside the result
+        result["max_rel_err_vs_oracle"] = errs.get("xcorr_f32_4096_f17")
+        for name, e in errs.items():
+            if extras and name in extras:
+                extras[name]["max_rel_err_vs_oracle"] = e
     gt.shutdown()
     print(json.dumps(result), flush=True)
 

@@ -113,13 +113,15 @@ typedef struct {
     double gflops;            /* flops / t_run / 1e9 */
     double gflops_per_w;      /* flops / e_run / 1e9  (= GFLOP/J) */
     double sclk_req_mhz;      /* requested clock limit (0 = default) */
-    double sclk_act_mhz;      /* mean reported graphics clock over kept samples */
+    double sclk_act_mhz;      /* mean graphics clock of the GPU-metrics updates first seen
+                               * inside the kept window (gt_window_clock); NaN if none */
     double mclk_mhz;          /* memory clock */
     double volt_v;            /* graphics voltage, NaN if not reported */
     double temp_c;            /* hotspot temperature at the end of the window */
     double window_s;          /* actual timed window */
     int64_t launches, n_samples, n_used;
-    int32_t throttled;        /* actual clock > 2 % below the requested limit */
+    int32_t throttled;        /* actual clock > 2 % below the requested limit (0 when
+                               * sclk_act_mhz is NaN) */
     int32_t flags;            /* bit 0: fake sensor, bit 1: fake DVFS */
 } gt_measurement;
 
@@ -142,6 +144,9 @@ typedef struct {
     double energy_j;          /* energy accumulator (monotone, wraps are unwrapped) */
     double energy_t_s;        /* firmware timestamp of that accumulator value, seconds */
     double sclk_mhz, mclk_mhz, volt_v, temp_c;  /* from the GPU metrics table (about 1 Hz) */
+    double metrics_t_s;       /* firmware timestamp of the GPU metrics table those four fields
+                               * came from, s (the energy accumulator's timestamp when the table
+                               * carries none; NaN if neither); the fake sensor gives t_s */
 } gt_sensor_sample;
 
 /* ---- lifecycle ---- */
@@ -238,10 +243,35 @@ int gt_power_model_band(const gt_power_model *model, const double *settable, siz
 int gt_energy_from_samples(const double *t_s, const double *p_w, size_t n, double t_start,
                            double t_stop, int64_t n_runs, double discard_s, double *e_run_j,
                            double *p_median_w, size_t *n_used);
+/* Graphics clock over a window of sensor readings (times ascending): the mean
+ * sclk_mhz of the GPU-metrics updates first observed at t_lo <= t_s <= t_hi.
+ * An update is a change of metrics_t_s from the reading before; readings
+ * before t_lo only establish the timestamp in force when the window opens
+ * (with none, the first reading in the window does), so a clock reported
+ * before the window is never counted.  The first observation of an update
+ * lags it by at most the sensor's metrics re-read period (50 ms) plus the
+ * poll period.  *sclk_mhz = NaN and *n_fresh = 0 when no update is seen.
+ * Errors: GT_E_INVAL. */
+int gt_window_clock(const gt_sensor_sample *samples, size_t n, double t_lo, double t_hi, double *sclk_mhz,
+                    size_t *n_fresh);
+/* The readings of the most recent measure_time_energy / measure_load window
+ * in this process (every reading the sampler took, the stabilisation prefix
+ * included), oldest first, and the window's host-time bounds: energy per run
+ * is gt_energy_from_samples over them with t_start, t_stop, the launch count
+ * and discard_s (readings with a non-finite power left out), with
+ * (t_stop - t_start) / launches replaced by the HIP-event time per launch.
+ * GT_E_STATE if no window has been measured; GT_E_CAPACITY as elsewhere. */
+int gt_measure_last_window(gt_sensor_sample *out, size_t capacity, size_t *n, double *t_start, double *t_stop);
 /* Objective selection over a measurement table (section V.A):
  * objective 0 = time (race-to-idle): min t_run, then e_run, then index;
  * objective 1 = energy: min e_run, then t_run, then index. */
 int gt_select(const gt_measurement *recs, size_t n, int objective, size_t *index);
+/* Pareto front of a measurement table (section V.A, the GFLOP/s versus
+ * GFLOP/s/W front): on_front[k] = 1 when no record j has t_run <= and
+ * e_run <= those of record k with at least one strictly lower, else 0.
+ * Records with equal (t_run, e_run) are all on the front or all off it.
+ * Errors: GT_E_INVAL. */
+int gt_pareto(const gt_measurement *recs, size_t n, int32_t *on_front);
 /* Algorithmic flop count: 2 per filter tap per output (padded taps counted). */
 double gt_problem_flops(const gt_problem *problem);
 /* LDS bytes the config's workgroup allocates (0 for read_path 1 and for the

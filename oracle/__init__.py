@@ -6,6 +6,7 @@ imports this module; only ``tests/``, ``__graft_entry__.smoke()`` and the
 Contents (each cites the passage it follows):
 
 * ``xcorr2d`` / ``conv_nhwc``      -- FP64 convolution (C library, ``xcorr_oracle.c``)
+* ``conv_nhwc_at``                -- the multi-channel definition at selected output pixels
 * ``xcorr2d_loops``               -- the same definition as pure-Python loops (tiny inputs)
 * ``power_model``                 -- Eq. 2 / Eq. 3 model, energy estimate, optimal clock,
                                      clock band, least-squares fit (section III.A and the
@@ -51,6 +52,9 @@ def _load():
         lib.oracle_conv_nhwc_f64.argtypes = [fp, i64, i64, i64, i64, fp, i64, i64, i64, i64, i64,
                                              dp, ctypes.c_int]
         lib.oracle_conv_nhwc_f64.restype = ctypes.c_int
+        lib.oracle_conv_nhwc_points_f64.argtypes = [fp, i64, i64, i64, i64, fp, i64, i64, i64, i64, i64,
+                                                    ctypes.POINTER(ctypes.c_int64), i64, dp, ctypes.c_int]
+        lib.oracle_conv_nhwc_points_f64.restype = ctypes.c_int
         lib.oracle_max_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -96,6 +100,25 @@ def conv_nhwc(x, wt, pad_h, pad_w, nthreads=0):
                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nthreads)
     if rc != 0:
         raise ValueError("bad conv sizes")
+    return out
+
+
+def conv_nhwc_at(x, wt, pad_h, pad_w, points, nthreads=0):
+    """conv_nhwc at selected output pixels: points is a sequence of (b, y, x);
+    returns [len(points)][c_out] float64."""
+    xa, px = _f32(x)
+    wa, pk = _f32(wt)
+    n, h, w, ci = xa.shape
+    co, fh, fw, ci2 = wa.shape
+    if ci != ci2:
+        raise ValueError("channel mismatch")
+    pts = np.ascontiguousarray(np.asarray(points, dtype=np.int64).reshape(-1, 3))
+    out = np.empty((pts.shape[0], co), dtype=np.float64)
+    rc = _load().oracle_conv_nhwc_points_f64(px, n, h, w, ci, pk, co, fh, fw, pad_h, pad_w,
+                                             pts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), pts.shape[0],
+                                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nthreads)
+    if rc != 0:
+        raise ValueError("bad conv sizes or points")
     return out
 
 

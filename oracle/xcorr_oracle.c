@@ -96,6 +96,50 @@ int oracle_conv_nhwc_f64(const float *x, int64_t n, int64_t h, int64_t w, int64_
     return 0;
 }
 
+/* The same definition at selected output pixels only: pts holds n_pts
+ * (b, y, x) triples; out receives c_out values per pixel, [n_pts][c_out].
+ * For checking outputs too large to compute whole on the CPU. */
+int oracle_conv_nhwc_points_f64(const float *x, int64_t n, int64_t h, int64_t w, int64_t c_in,
+                                const float *wt, int64_t c_out, int64_t fh, int64_t fw,
+                                int64_t ph, int64_t pw, const int64_t *pts, int64_t n_pts,
+                                double *out, int nthreads)
+{
+    if (n < 1 || c_in < 1 || c_out < 1 || fh < 1 || fw < 1 || ph < 0 || pw < 0 || n_pts < 0)
+        return -1;
+    const int64_t oh = h + 2 * ph - fh + 1, ow = w + 2 * pw - fw + 1;
+    for (int64_t k = 0; k < n_pts; ++k)
+        if (pts[3 * k] < 0 || pts[3 * k] >= n || pts[3 * k + 1] < 0 || pts[3 * k + 1] >= oh ||
+            pts[3 * k + 2] < 0 || pts[3 * k + 2] >= ow)
+            return -1;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+#endif
+    for (int64_t k = 0; k < n_pts; ++k) {
+        const int64_t b = pts[3 * k], y = pts[3 * k + 1], xo = pts[3 * k + 2];
+        for (int64_t co = 0; co < c_out; ++co) {
+            double s = 0.0;
+            for (int64_t r = 0; r < fh; ++r) {
+                const int64_t yi = y + r - ph;
+                if (yi < 0 || yi >= h)
+                    continue;
+                for (int64_t q = 0; q < fw; ++q) {
+                    const int64_t xi = xo + q - pw;
+                    if (xi < 0 || xi >= w)
+                        continue;
+                    const float *px = x + ((b * h + yi) * w + xi) * c_in;
+                    const float *pk = wt + ((co * fh + r) * fw + q) * c_in;
+                    for (int64_t ci = 0; ci < c_in; ++ci)
+                        s += (double)px[ci] * (double)pk[ci];
+                }
+            }
+            out[k * c_out + co] = s;
+        }
+    }
+    return 0;
+}
+
 int oracle_max_threads(void)
 {
 #ifdef _OPENMP

@@ -99,7 +99,7 @@ class BatchItem(ctypes.Structure):
 
 class SensorSample(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in ("t_s", "power_w", "energy_j", "energy_t_s", "sclk_mhz",
-                                               "mclk_mhz", "volt_v", "temp_c")]
+                                               "mclk_mhz", "volt_v", "temp_c", "metrics_t_s")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -145,6 +145,9 @@ def _load():
         "gt_energy_from_samples": ([P(c_double), P(c_double), c_size, c_double, c_double, ctypes.c_int64,
                                     c_double, P(c_double), P(c_double), P(c_size)], c_int),
         "gt_select": ([P(Measurement), c_size, c_int, P(c_size)], c_int),
+        "gt_pareto": ([P(Measurement), c_size, P(ctypes.c_int32)], c_int),
+        "gt_window_clock": ([P(SensorSample), c_size, c_double, c_double, P(c_double), P(c_size)], c_int),
+        "gt_measure_last_window": ([P(SensorSample), c_size, P(c_size), P(c_double), P(c_double)], c_int),
         "gt_problem_flops": ([P(Problem)], c_double),
         "gt_conv_lds_bytes": ([P(Problem), P(ConvConfig), P(ctypes.c_int64)], c_int),
         "gt_sensor_read": ([P(SensorSample)], c_int),
@@ -180,7 +183,8 @@ def _load():
 _lib = _load()
 EXPORTED = ("gt_init", "gt_shutdown", "gt_last_error", "gt_version", "conv2d_run", "conv2d_run_part",
             "tune_space_enumerate", "measure_time_energy", "measure_load", "fit_power_model", "gt_power_model_eval", "gt_power_model_throttle_clock",
-            "gt_power_model_band", "gt_energy_from_samples", "gt_select", "gt_problem_flops",
+            "gt_power_model_band", "gt_energy_from_samples", "gt_select", "gt_pareto", "gt_window_clock",
+            "gt_measure_last_window", "gt_problem_flops",
             "gt_conv_lds_bytes", "gt_sensor_read", "gt_settable_clocks", "gt_dvfs_state", "gt_power_cap_range", "gt_dvfs_set_backend", "gt_sensor_stale",
             "gt_fake_sensor_model", "gt_roofline_probe", "gt_mfma_probe", "gt_batch_pack", "conv2d_run_batched",
             "gt_graph_begin", "gt_graph_end", "gt_graph_launch", "gt_graph_destroy", "gt_sampler_start",
@@ -360,6 +364,44 @@ def select(records, objective):
     idx = ctypes.c_size_t(0)
     _check(_lib.gt_select(arr, len(records), {"time": 0, "energy": 1}[objective], ctypes.byref(idx)))
     return idx.value
+
+
+def pareto(records):
+    """Indices of the records not dominated in (t_run_s, e_run_j), both
+    minimised (the GFLOP/s versus GFLOP/s/W front), ascending."""
+    arr = (Measurement * max(len(records), 1))()
+    for k, r in enumerate(records):
+        arr[k].t_run_s = r["t_run_s"]
+        arr[k].e_run_j = r["e_run_j"]
+    flags = (ctypes.c_int32 * max(len(records), 1))()
+    _check(_lib.gt_pareto(arr, len(records), flags))
+    return [k for k in range(len(records)) if flags[k]]
+
+
+def _samples(samples):
+    arr = (SensorSample * max(len(samples), 1))()
+    nan = float("nan")
+    for k, d in enumerate(samples):
+        for n, _ in SensorSample._fields_:
+            setattr(arr[k], n, float(d.get(n, nan)))
+    return arr
+
+
+def window_clock(samples, t_lo, t_hi):
+    """(mean graphics clock of the GPU-metrics updates first seen in
+    [t_lo, t_hi], number of such updates); NaN when there is none."""
+    f, nf = ctypes.c_double(0), ctypes.c_size_t(0)
+    _check(_lib.gt_window_clock(_samples(samples), len(samples), float(t_lo), float(t_hi), ctypes.byref(f),
+                                ctypes.byref(nf)))
+    return f.value, nf.value
+
+
+def measure_last_window(capacity=1 << 16):
+    """(readings, t_start, t_stop) of the most recent measurement window."""
+    arr = (SensorSample * capacity)()
+    n, t0, t1 = ctypes.c_size_t(0), ctypes.c_double(0), ctypes.c_double(0)
+    _check(_lib.gt_measure_last_window(arr, capacity, ctypes.byref(n), ctypes.byref(t0), ctypes.byref(t1)))
+    return [arr[k].as_dict() for k in range(n.value)], t0.value, t1.value
 
 
 def problem_flops(problem):

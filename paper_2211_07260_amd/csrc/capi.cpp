@@ -260,4 +260,31 @@ int gt_select(const gt_measurement *recs, size_t n, int objective, size_t *index
     return GT_OK;
 }
 
+int gt_pareto(const gt_measurement *recs, size_t n, int32_t *on_front) {
+    clear_error();
+    if (n && (!recs || !on_front)) return set_error(GT_E_INVAL, "gt_pareto: null argument");
+    // sort by (t_run, e_run); a record is dominated exactly when some record
+    // before it in that order (a different point) has e_run <= its own, so one
+    // sweep keeping the running minimum of e_run over earlier points decides
+    std::vector<size_t> ord(n);
+    for (size_t k = 0; k < n; ++k) ord[k] = k;
+    std::sort(ord.begin(), ord.end(), [recs](size_t a, size_t b) {
+        if (recs[a].t_run_s != recs[b].t_run_s) return recs[a].t_run_s < recs[b].t_run_s;
+        return recs[a].e_run_j < recs[b].e_run_j;
+    });
+    double best_e = INFINITY;  // lowest e_run among points strictly before the current group
+    size_t k = 0;
+    while (k < n) {
+        size_t g = k;  // group of records at the same point
+        while (g < n && recs[ord[g]].t_run_s == recs[ord[k]].t_run_s && recs[ord[g]].e_run_j == recs[ord[k]].e_run_j)
+            ++g;
+        const gt_measurement &r = recs[ord[k]];
+        const int32_t front = r.e_run_j < best_e ? 1 : 0;
+        for (size_t j = k; j < g; ++j) on_front[ord[j]] = front;
+        best_e = std::min(best_e, r.e_run_j);
+        k = g;
+    }
+    return GT_OK;
+}
+
 }  // extern "C"

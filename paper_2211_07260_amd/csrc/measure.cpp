@@ -27,6 +27,28 @@ struct EventPair {
     }
 };
 
+// The readings of the most recent measurement window (gt_measure_last_window).
+struct LastWindow {
+    std::mutex mu;
+    bool valid = false;
+    std::vector<gt_sensor_sample> samples;
+    double t_start = 0, t_stop = 0;
+};
+
+LastWindow &last_window() {
+    static LastWindow w;
+    return w;
+}
+
+void record_last_window(const std::vector<gt_sensor_sample> &samples, double t_start, double t_stop) {
+    LastWindow &w = last_window();
+    std::lock_guard<std::mutex> lk(w.mu);
+    w.samples = samples;
+    w.t_start = t_start;
+    w.t_stop = t_stop;
+    w.valid = true;
+}
+
 }  // namespace
 
 namespace gt {
@@ -104,23 +126,33 @@ int measure_window(const std::function<int(hipStream_t)> &launch, double flops_p
     float win_ms = 0;
     GT_HIP_CHECK(hipEventElapsedTime(&win_ms, win.a, win.b));
 
-    // keep the samples after the stabilisation discard
-    std::vector<double> kept_p, kept_t;
-    double sclk_sum = 0;
-    int sclk_n = 0;
-    for (const gt_sensor_sample &smp : samples) {
-        if (smp.t_s < t_start + o.discard_s || smp.t_s > t_stop) continue;
-        if (!std::isfinite(smp.power_w)) continue;
-        kept_p.push_back(smp.power_w);
-        kept_t.push_back(smp.t_s);
-        if (std::isfinite(smp.sclk_mhz)) {
-            sclk_sum += smp.sclk_mhz;
-            ++sclk_n;
+    // Energy per run: the median of the finite power readings after the
+    // stabilisation discard (gt_energy_from_samples, the arithmetic the tests
+    // pin against the oracle) times the HIP-event time per launch.
+    std::vector<double> all_t, all_p;
+    all_t.reserve(samples.size());
+    all_p.reserve(samples.size());
+    for (const gt_sensor_sample &smp : samples)
+        if (std::isfinite(smp.power_w)) {
+            all_t.push_back(smp.t_s);
+            all_p.push_back(smp.power_w);
         }
-    }
-    if (kept_p.empty())
+    double e_host = 0, p_med = 0;
+    size_t n_used = 0;
+    const double t_lo = t_start + o.discard_s;
+    rc = gt_energy_from_samples(all_t.data(), all_p.data(), all_t.size(), t_start, t_stop, launched, o.discard_s,
+                                &e_host, &p_med, &n_used);
+    if (rc == GT_E_SENSOR)
         return set_error(GT_E_SENSOR, "measure: no power sample in the kept window (%zu samples, sensor errors %d)",
                          samples.size(), sensor_err.load());
+    if (rc) return rc;
+    std::vector<double> kept_p, kept_t;
+    for (size_t k = 0; k < all_t.size(); ++k)
+        if (all_t[k] >= t_lo && all_t[k] <= t_stop) {
+            kept_t.push_back(all_t[k]);
+            kept_p.push_back(all_p[k]);
+        }
+    record_last_window(samples, t_start, t_stop);
     // a hardware power reading that never changes under load is stale (the
     // fake sensor without noise is constant by design)
     if (!(state().flags & GT_INIT_FAKE_SENSOR) &&
@@ -133,8 +165,8 @@ int measure_window(const std::function<int(hipStream_t)> &launch, double flops_p
     m.window_s = win_ms * 1e-3;
     m.t_run_s = m.window_s / (double)launched;
     m.n_samples = (int64_t)samples.size();
-    m.n_used = (int64_t)kept_p.size();
-    m.p_median_w = median_of(kept_p);
+    m.n_used = (int64_t)n_used;
+    m.p_median_w = p_med;
     m.p_min_w = *std::min_element(kept_p.begin(), kept_p.end());
     m.p_max_w = *std::max_element(kept_p.begin(), kept_p.end());
     m.e_run_j = m.p_median_w * m.t_run_s;
@@ -158,17 +190,67 @@ int measure_window(const std::function<int(hipStream_t)> &launch, double flops_p
     m.gflops = flops_per_launch / m.t_run_s * 1e-9;
     m.gflops_per_w = flops_per_launch / m.e_run_j * 1e-9;
     m.sclk_req_mhz = dvfs_requested_mhz();
-    m.sclk_act_mhz = sclk_n ? sclk_sum / sclk_n : NAN;
+    size_t n_fresh = 0;
+    gt_window_clock(samples.data(), samples.size(), t_lo, t_stop, &m.sclk_act_mhz, &n_fresh);
     const gt_sensor_sample &tail = samples.back();
     m.mclk_mhz = tail.mclk_mhz;
     m.volt_v = tail.volt_v;
     m.temp_c = tail.temp_c;
-    m.throttled = (m.sclk_req_mhz > 0 && sclk_n && m.sclk_act_mhz < 0.98 * m.sclk_req_mhz) ? 1 : 0;
+    m.throttled = (m.sclk_req_mhz > 0 && std::isfinite(m.sclk_act_mhz) && m.sclk_act_mhz < 0.98 * m.sclk_req_mhz)
+                      ? 1
+                      : 0;
     m.flags = ((state().flags & GT_INIT_FAKE_SENSOR) ? 1 : 0) | ((state().flags & GT_INIT_FAKE_DVFS) ? 2 : 0);
     return GT_OK;
 }
 
 }  // namespace gt
+
+extern "C" int gt_window_clock(const gt_sensor_sample *samples, size_t n, double t_lo, double t_hi,
+                               double *sclk_mhz, size_t *n_fresh) {
+    clear_error();
+    if ((n && !samples) || !sclk_mhz) return set_error(GT_E_INVAL, "gt_window_clock: null argument");
+    double seen = NAN;  // metrics timestamp in force; NaN = not established yet
+    bool have_seen = false;
+    double sum = 0;
+    size_t cnt = 0;
+    for (size_t k = 0; k < n; ++k) {
+        const gt_sensor_sample &s = samples[k];
+        if (s.t_s > t_hi) break;
+        const double ts = s.metrics_t_s;
+        if (!std::isfinite(ts)) continue;
+        if (s.t_s < t_lo || !have_seen) {
+            seen = ts;
+            have_seen = true;
+            continue;
+        }
+        if (ts == seen) continue;
+        seen = ts;
+        if (std::isfinite(s.sclk_mhz)) {
+            sum += s.sclk_mhz;
+            ++cnt;
+        }
+    }
+    *sclk_mhz = cnt ? sum / (double)cnt : NAN;
+    if (n_fresh) *n_fresh = cnt;
+    return GT_OK;
+}
+
+extern "C" int gt_measure_last_window(gt_sensor_sample *out, size_t capacity, size_t *n, double *t_start,
+                                      double *t_stop) {
+    clear_error();
+    if (!n || (capacity && !out)) return set_error(GT_E_INVAL, "gt_measure_last_window: bad argument");
+    LastWindow &w = last_window();
+    std::lock_guard<std::mutex> lk(w.mu);
+    if (!w.valid) return set_error(GT_E_STATE, "gt_measure_last_window: no window measured yet");
+    *n = w.samples.size();
+    for (size_t k = 0; k < w.samples.size() && k < capacity; ++k) out[k] = w.samples[k];
+    if (t_start) *t_start = w.t_start;
+    if (t_stop) *t_stop = w.t_stop;
+    if (w.samples.size() > capacity)
+        return set_error(GT_E_CAPACITY, "gt_measure_last_window: %zu samples, capacity %zu", w.samples.size(),
+                         capacity);
+    return GT_OK;
+}
 
 extern "C" int gt_sensor_stale(const double *t_s, const double *p_w, size_t n, double min_span_s) {
     clear_error();

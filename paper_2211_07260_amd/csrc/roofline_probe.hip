@@ -8,20 +8,41 @@
 
 namespace gt {
 
+// Uniform value in [0.5, 1) from a 32-bit integer hash (scalar when k is).
+__device__ __forceinline__ float hashed_unit(uint32_t k) {
+    k ^= k >> 16;
+    k *= 0x7FEB352Du;
+    k ^= k >> 15;
+    k *= 0x846CA68Bu;
+    k ^= k >> 16;
+    return __uint_as_float(0x3F000000u | (k >> 9));
+}
+
 // 32 independent accumulators, 8 input registers, weights from SGPRs:
-// 256 FMAs per loop trip per lane.
-__global__ __launch_bounds__(256) void fma_peak_kernel(float *out, const float *w, int iters) {
-    float acc[32], x[8];
+// 256 FMAs per loop trip per lane.  Operands are hashed per workgroup and
+// lane (no memory is read).  kMix: after every trip the inputs take the
+// accumulators' mantissa bits (x in [1, 2)), so the operands keep changing
+// the way a real kernel's do (the power a calibration load draws depends on
+// operand toggling); the probe leaves them fixed to time the bare FMA rate.
+template <bool kMix>
+__global__ __launch_bounds__(256) void fma_peak_kernel(float *out, int iters) {
+    float acc[32], x[8], s[8];
 #pragma unroll
     for (int k = 0; k < 32; ++k) acc[k] = 0.0f;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) x[k] = (float)(threadIdx.x + k) * 1e-3f;
+    for (int k = 0; k < 8; ++k) {
+        x[k] = 2.0f * hashed_unit(blockIdx.x * 2048u + threadIdx.x * 8u + k);
+        s[k] = hashed_unit(0x9E3779B9u ^ (blockIdx.x * 8u + k));
+    }
     for (int it = 0; it < iters; ++it) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const float s = w[j];
 #pragma unroll
-            for (int k = 0; k < 32; ++k) acc[k] = __builtin_fmaf(x[(k + j) & 7], s, acc[k]);
+            for (int k = 0; k < 32; ++k) acc[k] = __builtin_fmaf(x[(k + j) & 7], s[j], acc[k]);
+        }
+        if (kMix) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) x[k] = __uint_as_float((__float_as_uint(acc[4 * k + (it & 3)]) & 0x007FFFFFu) | 0x3F800000u);
         }
     }
     float t = 0.0f;
@@ -82,7 +103,7 @@ int load_work(int kind, size_t bytes, double *work) {
     switch (kind) {
         case GT_LOAD_FP32_FMA: {
             const int blocks = cus * 8;
-            if ((size_t)(blocks * 256 + 8) * sizeof(float) > bytes)
+            if ((size_t)blocks * 256 * sizeof(float) > bytes)
                 return set_error(GT_E_INVAL, "measure_load: buffer too small for the FMA load");
             *work = 2.0 * 256.0 * kLoadFmaIters * (double)blocks * 256;
             return GT_OK;
@@ -110,7 +131,7 @@ int launch_load(int kind, void *buf, size_t bytes, hipStream_t s) {
     float *out = static_cast<float *>(buf);
     if (kind == GT_LOAD_FP32_FMA) {
         const int blocks = cus * 8;
-        hipLaunchKernelGGL(fma_peak_kernel, dim3(blocks), dim3(256), 0, s, out, out + blocks * 256, kLoadFmaIters);
+        hipLaunchKernelGGL(fma_peak_kernel<true>, dim3(blocks), dim3(256), 0, s, out, kLoadFmaIters);
     } else if (kind == GT_LOAD_BF16_MFMA) {
         hipLaunchKernelGGL(mfma_peak_kernel, dim3(cus * 2), dim3(256), 0, s, out, kLoadMfmaIters);
     } else {
@@ -138,16 +159,15 @@ extern "C" int gt_roofline_probe(void *d_buf, size_t bytes, void *hip_stream, do
     hipStream_t s = (hipStream_t)hip_stream;
     const int cus = state().dev.cu_count > 0 ? state().dev.cu_count : 256;
     const int blocks = cus * 8, iters = 2048;
-    if ((size_t)(blocks * 256 + 8) * sizeof(float) > bytes)
+    if ((size_t)blocks * 256 * sizeof(float) > bytes)
         return set_error(GT_E_INVAL, "gt_roofline_probe: buffer too small");
     float *out = static_cast<float *>(d_buf);
-    const float *w = out + blocks * 256;  // 8 filter-like values past the outputs (contents irrelevant)
     hipEvent_t a, b;
     GT_HIP_CHECK(hipEventCreate(&a));
     GT_HIP_CHECK(hipEventCreate(&b));
-    hipLaunchKernelGGL(fma_peak_kernel, dim3(blocks), dim3(256), 0, s, out, w, iters);  // warm
+    hipLaunchKernelGGL(fma_peak_kernel<false>, dim3(blocks), dim3(256), 0, s, out, iters);  // warm
     GT_HIP_CHECK(hipEventRecord(a, s));
-    hipLaunchKernelGGL(fma_peak_kernel, dim3(blocks), dim3(256), 0, s, out, w, iters);
+    hipLaunchKernelGGL(fma_peak_kernel<false>, dim3(blocks), dim3(256), 0, s, out, iters);
     GT_HIP_CHECK(hipEventRecord(b, s));
     GT_HIP_CHECK(hipEventSynchronize(b));
     float ms = 0;

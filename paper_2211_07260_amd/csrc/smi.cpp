@@ -204,6 +204,13 @@ int refresh_metrics_locked(double now) {
     c.mclk_mhz = m.current_uclk != NA16 ? (double)m.current_uclk : NAN;
     c.volt_v = (m.voltage_gfx != NA16 && m.voltage_gfx != 0) ? m.voltage_gfx * 1e-3 : NAN;
     c.temp_c = m.temperature_hotspot != NA16 ? (double)m.temperature_hotspot : NAN;
+    // the firmware's timestamp of this table (10 ns units) tells a refreshed
+    // table from a re-read of the same one; the energy accumulator's
+    // timestamp stands in when the table carries none
+    if (m.firmware_timestamp != 0 && m.firmware_timestamp != UINT64_MAX)
+        c.metrics_t_s = (double)m.firmware_timestamp * 1e-8;
+    else
+        c.metrics_t_s = c.energy_t_s;
     g_smi.metrics_t = now;
     return GT_OK;
 }
@@ -299,6 +306,7 @@ int sensor_read(gt_sensor_sample *out) {
         out->mclk_mhz = NAN;
         out->volt_v = NAN;
         out->temp_c = NAN;
+        out->metrics_t_s = out->t_s;
         return GT_OK;
     }
     int rc = smi_open_locked();

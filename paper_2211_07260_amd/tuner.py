@@ -147,14 +147,11 @@ def optima(rows):
 
 
 def pareto(rows):
-    """Non-dominated rows in (GFLOP/s, GFLOP/s/W)."""
+    """Non-dominated rows in (GFLOP/s, GFLOP/s/W) by the library's gt_pareto,
+    fastest first."""
     ok = [r for r in rows if "error" not in r and "e_run_j" in r]
-    out = []
-    for a in ok:
-        if not any(b["t_run_s"] <= a["t_run_s"] and b["e_run_j"] <= a["e_run_j"]
-                   and (b["t_run_s"] < a["t_run_s"] or b["e_run_j"] < a["e_run_j"]) for b in ok):
-            out.append(a)
-    return sorted(out, key=lambda r: r["t_run_s"])
+    front = [ok[k] for k in gt.pareto(ok)] if ok else []
+    return sorted(front, key=lambda r: (r["t_run_s"], r["e_run_j"]))
 
 
 # ---- model-steered clock search (section V.D) ----
@@ -209,6 +206,30 @@ def calibrate(kind, buf, settable, p_max, n_fit=5, window_s=1.0, discard_s=0.3):
     return {"kind": kind, "fit_points": pts, "model": model.as_dict()}
 
 
+def pick_calibration(load_power_w, workload_power_w):
+    """The synthetic load to calibrate the power model with: the paper fits
+    to a load that fully occupies the device (section V.D), so a load drawing
+    less power than the workload itself at the default clock cannot stand in
+    for it.  Among the loads whose median power is at least the workload's,
+    the one drawing the most; None when no load reaches it (calibrate with
+    the workload instead).  load_power_w: {kind: watts}."""
+    ok = {k: p for k, p in load_power_w.items() if p == p and p >= workload_power_w}
+    if not ok:
+        return None
+    return max(sorted(ok), key=lambda k: ok[k])
+
+
+def choose_calibration(buf, workload_measure, kinds=None, window_s=1.0, discard_s=0.3):
+    """Measure the synthetic loads and the workload (workload_measure() ->
+    dict with p_median_w) at the default clock, and pick the calibration load
+    by pick_calibration.  Returns (kind or None, report)."""
+    kinds = kinds if kinds is not None else (gt.LOAD_FP32_FMA, gt.LOAD_BF16_MFMA, gt.LOAD_COPY)
+    powers = {k: gt.measure_load(k, buf, window_s=window_s, discard_s=discard_s)["p_median_w"] for k in kinds}
+    p_work = workload_measure()["p_median_w"]
+    kind = pick_calibration(powers, p_work)
+    return kind, {"load_power_w": powers, "workload_power_w": p_work, "kind": kind}
+
+
 def steered_search(measure, configs, settable, p_max, n_fit=5, rel_half=0.1, fit_config=None, model=None):
     """The paper's procedure (section V.D): fit Eq. 2/3 to <= n_fit power
     readings of one fully-loading config (fit_readings), take the clock
@@ -249,7 +270,7 @@ def exhaustive_clock_search(measure, configs, settable):
     return {"rows": rows, "best": best, "points_measured": len(rows)}
 
 
-# ---- the tuning methods compared in the experiments (section VI.A) ----
+# ---- the tuning methods compared in the experiments (section V.A) ----
 
 METHODS = ("race_to_idle", "energy_to_solution_maxclock", "race_to_idle_clocks", "energy_to_solution_clocks",
            "global_energy_to_solution")

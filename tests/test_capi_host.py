@@ -263,3 +263,57 @@ def test_sensor_stale_rule():
     assert not gt.sensor_stale(t[:3], [900.0] * 3, 0.5)     # spans only 0.4 s
     assert not gt.sensor_stale([0.0], [900.0], 0.0)         # one reading proves nothing
     assert not gt.sensor_stale([], [], 0.5)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_pareto_matches_oracle(seed):
+    # values drawn from small sets, so exact ties in one or both objectives
+    # are common; the library's sort-and-sweep must equal brute force
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 60))
+    rows = [{"t_run": float(rng.integers(1, 8)), "e_run": float(rng.integers(1, 8))} for _ in range(n)]
+    if seed == 0:
+        rows = [{"t_run": 2.0, "e_run": 3.0}] * 4  # all identical: all on the front
+    want = om.pareto_front(rows)
+    got = gt.pareto([{"t_run_s": r["t_run"], "e_run_j": r["e_run"]} for r in rows])
+    assert got == want
+
+
+def test_pareto_empty_and_single():
+    assert gt.pareto([]) == []
+    assert gt.pareto([{"t_run_s": 1.0, "e_run_j": 1.0}]) == [0]
+
+
+def _smp(t, sclk, mts, p=1000.0):
+    return {"t_s": t, "power_w": p, "energy_j": 0.0, "energy_t_s": mts, "sclk_mhz": sclk, "mclk_mhz": 0.0,
+            "volt_v": float("nan"), "temp_c": 50.0, "metrics_t_s": mts}
+
+
+def test_window_clock_ignores_stale_pre_window_metrics():
+    # metrics table refreshed at firmware times 10.0 (idle, 165 MHz), 11.0 and
+    # 12.0 (loaded); the sensor re-reads it every few ms.  Kept window 0.5..2.5
+    trace = ([_smp(0.01 * k, 165.0, 10.0) for k in range(80)]            # 0.00-0.79: idle table
+             + [_smp(0.8 + 0.01 * k, 2100.0, 11.0) for k in range(100)]  # 0.80-1.79: first loaded table
+             + [_smp(1.8 + 0.01 * k, 2300.0, 12.0) for k in range(100)])  # 1.80-2.79
+    # both loaded updates are first seen inside the window: mean 2200
+    f, n = gt.window_clock(trace, 0.5, 2.5)
+    assert n == 2 and f == pytest.approx(2200.0, rel=1e-15)
+    # a window opening after the first loaded update was seen counts only the
+    # second one, though the first is still what the sensor reports at 1.0 s
+    f, n = gt.window_clock(trace, 1.0, 2.5)
+    assert n == 1 and f == 2300.0
+    # a window with no refresh inside: NaN (the 165 MHz reading is never used)
+    f, n = gt.window_clock(trace, 0.2, 0.7)
+    assert n == 0 and f != f
+    # no reading before the window: the first one in it only sets the
+    # timestamp in force (it may predate the window)
+    f, n = gt.window_clock(trace[30:], 0.0, 1.5)
+    assert n == 1 and f == 2100.0
+
+
+def test_window_clock_skips_invalid_timestamps_and_clocks():
+    nan = float("nan")
+    trace = [_smp(0.0, 500.0, 1.0), _smp(0.1, 900.0, nan), _smp(0.2, nan, 2.0), _smp(0.3, 1800.0, 3.0),
+             _smp(0.4, 1900.0, 3.0)]
+    f, n = gt.window_clock(trace, 0.05, 1.0)
+    assert n == 1 and f == 1800.0  # 2.0 carries no clock, 3.0 counts once

@@ -275,3 +275,35 @@ def test_refused_first_knob_change_leaves_no_state_file(gt, tmp_path, monkeypatc
     finally:
         gt.shutdown()
         gt.set_dvfs_backend(None)
+
+
+@pytest.mark.parametrize("noise_w", [15.0, 60.0])
+def test_noisy_window_energy_matches_oracle(gt, noise_w):
+    # the fake sensor adds seeded Gaussian noise, so the kept readings differ
+    # and the median and discard bound decide the result; the record must
+    # equal the oracle's median-power energy over the same readings
+    from oracle import measure as om
+    gt.init(0, gt.INIT_FAKE_SENSOR | gt.INIT_FAKE_DVFS)
+    try:
+        m = gt.power_model(MODEL["p_idle"], MODEL["alpha"], MODEL["beta"], MODEL["tau"], MODEL["p_max"])
+        gt.fake_sensor_model(m, noise_w=noise_w, seed=7)
+        img, w, out = bufs()
+        prob = gt.xcorr_problem(1024, 1024, 17, 17)
+        for f, discard in ((1100, 0.05), (2000, 0.12)):
+            r = gt.measure_time_energy(prob, (32, 8, 4, 2, 0, 0), img, w, out, gt.clock(gt.CLOCK_SCLK_MHZ, f),
+                                       window_s=0.3, discard_s=discard)
+            smp, t0, t1 = gt.measure_last_window()
+            assert len(smp) == r["n_samples"] and t0 < t1
+            ts = [s["t_s"] for s in smp]
+            ps = [s["power_w"] for s in smp]
+            assert len(set(ps)) > 10  # the noise makes the readings differ
+            e_o, p_o, t_o, n_o = om.energy_per_run(ts, ps, t0, t1, r["launches"], discard)
+            assert r["p_median_w"] == p_o and r["n_used"] == n_o
+            assert r["e_run_j"] == p_o * r["t_run_s"]
+            # the host-time window and the HIP-event window agree closely
+            assert t_o == pytest.approx(r["t_run_s"], rel=0.05)
+            assert r["p_min_w"] == min(p for t, p in zip(ts, ps) if t0 + discard <= t <= t1)
+            # every fake reading is a fresh metrics update at the set clock
+            assert r["sclk_act_mhz"] == float(f) and not r["throttled"]
+    finally:
+        gt.shutdown()

@@ -1,6 +1,6 @@
 """The five tuning methods of the paper's experiments (race-to-idle, lowest
 energy at the top clock, the two two-step methods, and the global energy
-optimum; section VI.A) on a simulated device (CPU): each method's choice
+optimum; section V.A) on a simulated device (CPU): each method's choice
 must equal its definition evaluated by brute force over the full (config,
 clock) table with the oracle's selection rule, every (config, clock) is
 measured once, and the orderings the definitions imply hold."""

@@ -133,3 +133,35 @@ def test_multichannel_delta_weight_selects_channel_and_shift():
     padded = np.pad(xf[0, :, :, 1], 1)
     assert np.array_equal(got[0, :, :, 0], padded[0:8, 2:10])
     assert np.array_equal(got[0, :, :, 1], xf[0, :, :, 3].astype(np.float64))
+
+
+def test_multichannel_points_brute_force_integers():
+    # integer data: the sampled-pixel oracle equals a pure-Python loop of the
+    # definition exactly, at interior, edge and corner pixels
+    g = np.random.default_rng(3)
+    x = g.integers(-3, 4, (2, 6, 7, 3)).astype(np.float32)
+    wt = g.integers(-3, 4, (4, 3, 5, 3)).astype(np.float32)
+    ph, pw = 1, 2
+    pts = [(0, 0, 0), (1, 5, 6), (0, 2, 3), (1, 0, 6), (0, 5, 0)]
+    got = oracle.conv_nhwc_at(x, wt, ph, pw, pts)
+    for k, (b, y, xo) in enumerate(pts):
+        for co in range(4):
+            s = 0.0
+            for r in range(3):
+                for q in range(5):
+                    yi, xi = y + r - ph, xo + q - pw
+                    if 0 <= yi < 6 and 0 <= xi < 7:
+                        s += sum(float(x[b, yi, xi, c]) * float(wt[co, r, q, c]) for c in range(3))
+            assert got[k, co] == s
+
+
+def test_multichannel_points_equal_full_and_reject_outside():
+    g = np.random.default_rng(4)
+    x = g.standard_normal((2, 9, 8, 5)).astype(np.float32)
+    wt = g.standard_normal((3, 5, 5, 5)).astype(np.float32)
+    full = oracle.conv_nhwc(x, wt, 2, 2)
+    pts = [(b, y, xo) for b in range(2) for y in range(9) for xo in range(8)]
+    got = oracle.conv_nhwc_at(x, wt, 2, 2, pts)
+    assert np.array_equal(got, full.reshape(-1, 3))
+    with pytest.raises(ValueError):
+        oracle.conv_nhwc_at(x, wt, 2, 2, [(0, 9, 0)])

@@ -93,3 +93,12 @@ def test_fit_readings_start_at_top_clock_and_skip_throttled():
     assert pts[0]["clock_mhz"] == 2400.0 and pts[0]["throttled"]
     assert len(pts) <= 5
     assert all(p["clock_mhz"] <= pts[0]["sclk_act_mhz"] for p in pts[1:])
+
+
+def test_pick_calibration_needs_a_full_load():
+    from paper_2211_07260_amd import tuner
+    # a register-only FMA load below the convolution's power is not a stand-in
+    assert tuner.pick_calibration({0: 735.0, 1: 1350.0, 2: 895.0}, 1034.0) == 1
+    assert tuner.pick_calibration({0: 735.0, 2: 895.0}, 1034.0) is None
+    assert tuner.pick_calibration({0: 1100.0, 1: 1100.0}, 1034.0) == 0  # tie: lower kind
+    assert tuner.pick_calibration({0: float("nan"), 1: 1040.0}, 1034.0) == 1
