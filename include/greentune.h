@@ -373,6 +373,25 @@ int gt_batch_pack(const gt_batch_item *items, int32_t n_items, const gt_conv_con
 int conv2d_run_batched(const void *d_blob, int32_t n_items, int64_t total_tiles, int32_t filt,
                        const gt_conv_config *cfg, int32_t grid_blocks, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): conv2d_run_batched
+ * without the caller's descriptor blob.  Takes the items as in gt_batch_pack
+ * (host array, read during the call only) and runs the same persistent
+ * kernel, so every output is bit for bit that of conv2d_run_batched with the
+ * same items, config and grid.  The descriptors go to a device array the
+ * library holds for the life of the process, one per GPU, of
+ * GT_BATCH_NOALLOC_MAX_ITEMS 48-byte records (192 KiB); they are written
+ * there by small kernels on hip_stream ahead of the launch (the descriptors
+ * travel as kernel arguments), so the call allocates nothing, on the device
+ * or the host, and returns without waiting.  Every call on a GPU shares that
+ * array: calls on one stream are ordered, but calls that overlap on one GPU
+ * (on different streams, or from several threads) race and give undefined
+ * results.  Errors: GT_E_INVAL (n_items outside 1..GT_BATCH_NOALLOC_MAX_ITEMS,
+ * bad items), GT_E_UNSUPPORTED (config), GT_E_STATE (no device), GT_E_HIP. */
+#define GT_BATCH_NOALLOC_MAX_ITEMS 4096
+int conv2d_run_batched_noalloc(const gt_batch_item *items, int32_t n_items, const gt_conv_config *cfg,
+                               int32_t grid_blocks, void *hip_stream);
+
 /* Graph capture of the launches issued on hip_stream between begin and end
  * (hipStreamBeginCapture / EndCapture / Instantiate).  *graph_exec is an
  * opaque executable graph owned by the caller until gt_graph_destroy. */

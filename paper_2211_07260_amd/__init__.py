@@ -163,6 +163,7 @@ def _load():
                            P(ctypes.c_int64)], c_int),
         "conv2d_run_batched": ([vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P(ConvConfig),
                                 ctypes.c_int32, vp], c_int),
+        "conv2d_run_batched_noalloc": ([P(BatchItem), ctypes.c_int32, P(ConvConfig), ctypes.c_int32, vp], c_int),
         "gt_graph_begin": ([vp], c_int),
         "gt_graph_end": ([vp, P(vp)], c_int),
         "gt_graph_launch": ([vp, vp], c_int),
@@ -187,6 +188,7 @@ EXPORTED = ("gt_init", "gt_shutdown", "gt_last_error", "gt_version", "conv2d_run
             "gt_measure_last_window", "gt_problem_flops",
             "gt_conv_lds_bytes", "gt_sensor_read", "gt_settable_clocks", "gt_dvfs_state", "gt_power_cap_range", "gt_dvfs_set_backend", "gt_sensor_stale",
             "gt_fake_sensor_model", "gt_roofline_probe", "gt_mfma_probe", "gt_batch_pack", "conv2d_run_batched",
+            "conv2d_run_batched_noalloc",
             "gt_graph_begin", "gt_graph_end", "gt_graph_launch", "gt_graph_destroy", "gt_sampler_start",
             "gt_sampler_stop", "gt_sensor_busy", "gt_ffg_centrality")
 
@@ -539,6 +541,21 @@ class Batch:
     def run(self, grid_blocks=0, stream=None):
         _check(_lib.conv2d_run_batched(_ptr(self.blob), self.n, self.total_tiles, self.filt, ctypes.byref(self.cfg),
                                        grid_blocks, _stream(stream)))
+
+
+BATCH_NOALLOC_MAX_ITEMS = 4096
+
+
+def conv2d_run_batched_noalloc(convs, cfg, grid_blocks=0, stream=None):
+    """The batched launch without a descriptor blob: the library writes the
+    descriptors into its own per-GPU device array (at most
+    BATCH_NOALLOC_MAX_ITEMS items), so nothing is allocated.  convs as for
+    Batch.  Calls that overlap on one GPU race on that array."""
+    items = (BatchItem * max(1, len(convs)))()
+    for k, (di, dw, do, oh, ow, f) in enumerate(convs):
+        items[k] = BatchItem(di.data_ptr(), dw.data_ptr(), do.data_ptr(), oh, ow, f, f)
+    _check(_lib.conv2d_run_batched_noalloc(items, len(convs), ctypes.byref(as_config(cfg)), int(grid_blocks),
+                                           _stream(stream)))
 
 
 class Graph:

@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "gt_internal.hpp"
@@ -111,7 +112,120 @@ int64_t batch_lds_bytes(const gt_conv_config &c, int fw) {
     return xcorr_lds_bytes(p, c);
 }
 
+// Descriptor of item k of a batch whose earlier items cover *tiles tiles;
+// advances *tiles.  fw: the batch's filter size.
+int fill_desc(const gt_batch_item &it, int k, int fw, const gt_conv_config &cfg, int64_t *tiles, BatchDesc *d) {
+    if (!it.d_in || !it.d_filt || !it.d_out || it.out_h < 1 || it.out_w < 1)
+        return set_error(GT_E_INVAL, "batch: item %d is not valid", k);
+    if (it.filt_h != fw || it.filt_w != fw)
+        return set_error(GT_E_INVAL, "batch: item %d: all items need the same square filter (%d)", k, fw);
+    if ((int64_t)(it.out_h + fw - 1) * (it.out_w + fw - 1) >= (int64_t)1 << 31)
+        return set_error(GT_E_INVAL, "batch: item %d too large", k);
+    const int64_t ox = (int64_t)cfg.block_size_x * cfg.tile_size_x, oy = (int64_t)cfg.block_size_y * cfg.tile_size_y;
+    const int64_t tx = (it.out_w + ox - 1) / ox, ty = (it.out_h + oy - 1) / oy;
+    d->in = static_cast<const float *>(it.d_in);
+    d->w = static_cast<const float *>(it.d_filt);
+    d->out = static_cast<float *>(it.d_out);
+    d->out_h = it.out_h;
+    d->out_w = it.out_w;
+    d->tiles_x = (int32_t)tx;
+    d->flags = ((((uintptr_t)it.d_in & 15) == 0) ? 1 : 0) |
+               (((((uintptr_t)it.d_out & 15) == 0) && it.out_w % 4 == 0) ? 2 : 0);
+    d->tile_begin = *tiles;
+    *tiles += tx * ty;
+    return GT_OK;
+}
+
+// One persistent launch over a descriptor array in device memory (see
+// conv2d_run_batched).
+int launch_batched(const BatchDesc *desc, int32_t n_items, int64_t total_tiles, int32_t filt,
+                   const gt_conv_config &cfg, int32_t grid_blocks, hipStream_t stream) {
+    const int64_t lds = batch_lds_bytes(cfg, filt);
+    if (lds > state().dev.lds_per_block) return set_error(GT_E_UNSUPPORTED, "batched: LDS tile too large");
+    const void *fn = batched_fn(cfg.tile_size_x, cfg.tile_size_y, filt);
+    if (lds > 65536) GT_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int threads = cfg.block_size_x * cfg.block_size_y;
+    int64_t grid;
+    if (grid_blocks <= 0) {
+        // The resident capacity; twice that for the VALU-bound filters (9 and
+        // up): workgroups beyond the resident ones start as others finish,
+        // which evens out the last round (measured +2-6 % for 17x17, while
+        // the HBM-bound 3x3 and 5x5 lose 2-3 % the same way, and a grid
+        // balanced to equal tiles per workgroup loses 10 % at 17x17).  A
+        // multiple of 8 for the per-XCD tile order.
+        int per_cu = 0;
+        GT_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, (size_t)lds));
+        const int64_t resident = (int64_t)std::max(1, per_cu) * std::max(1, state().dev.cu_count);
+        grid = std::min<int64_t>(total_tiles, (filt >= 9 ? 2 : 1) * resident);
+        if (grid >= 8) grid = grid / 8 * 8;
+    } else {
+        grid = std::min<int64_t>(grid_blocks, total_tiles);
+    }
+    const int pitch = (int)((cfg.block_size_x * cfg.tile_size_x + filt - 1 + 3) / 4 * 4 +
+                            4 * (cfg.use_lds_padding ? 1 : 0));
+    int n = n_items;
+    int64_t tt = total_tiles;
+    void *args[] = {&desc, &n, &tt, (void *)&pitch};
+    GT_HIP_CHECK(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(cfg.block_size_x, cfg.block_size_y), args,
+                                 (size_t)lds, stream));
+    return GT_OK;
+}
+
 }  // namespace
+
+// ---- the allocation-free batched launch ----
+//
+// Its descriptors live in `scratch`, a file-scope device array (one copy per
+// GPU, held until the process ends), instead of a caller-provided device
+// blob.  They reach it through kernel arguments: the host packs up to
+// kUploadChunk descriptors into an argument block and a one-wave kernel
+// stores them, so the call needs neither device allocation nor a host
+// staging buffer that must outlive it, and stays asynchronous on the stream.
+// In host code `scratch` names a host-side stand-in: kernels get the device
+// address hipGetSymbolAddress returns, kept per device.
+constexpr int kUploadChunk = 64;
+struct DescChunk {
+    int32_t first, n;
+    int32_t pad[2];
+    BatchDesc d[kUploadChunk];
+};
+static_assert(sizeof(DescChunk) <= 4096 - 64, "kernel-argument block");
+
+static __device__ __align__(256) BatchDesc scratch[GT_BATCH_NOALLOC_MAX_ITEMS];
+
+__global__ __launch_bounds__(64) void batch_desc_upload_kernel(BatchDesc *dst, DescChunk chunk) {
+    const int k = threadIdx.x;
+    if (k < chunk.n) {
+        // 48 bytes: dword reads of the argument block (8-byte aligned), three
+        // 16-byte vector stores (the array is 256-byte aligned, a record 48)
+        typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
+        const unsigned int *src = reinterpret_cast<const unsigned int *>(&chunk.d[k]);
+        u32x4v *to = reinterpret_cast<u32x4v *>(dst + chunk.first + k);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) to[q] = u32x4v{src[4 * q], src[4 * q + 1], src[4 * q + 2], src[4 * q + 3]};
+    }
+}
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static BatchDesc *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+static int scratch_ptr(BatchDesc **out) {
+    int dev = -1;
+    GT_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return set_error(GT_E_STATE, "batched (no allocation): device %d", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        GT_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return set_error(GT_E_HIP, "batched (no allocation): no device address for the descriptor array");
+        g_scratch_ptr[dev] = static_cast<BatchDesc *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return GT_OK;
+}
+
 }  // namespace gt
 
 using namespace gt;
@@ -130,26 +244,9 @@ int gt_batch_pack(const gt_batch_item *items, int32_t n_items, const gt_conv_con
     *blob_bytes = need;
     std::vector<BatchDesc> d((size_t)n_items);
     int64_t tiles = 0;
-    const int64_t ox = (int64_t)cfg->block_size_x * cfg->tile_size_x, oy = (int64_t)cfg->block_size_y * cfg->tile_size_y;
     for (int32_t k = 0; k < n_items; ++k) {
-        const gt_batch_item &it = items[k];
-        if (!it.d_in || !it.d_filt || !it.d_out || it.out_h < 1 || it.out_w < 1)
-            return set_error(GT_E_INVAL, "gt_batch_pack: item %d is not valid", k);
-        if (it.filt_h != fw || it.filt_w != fw)
-            return set_error(GT_E_INVAL, "gt_batch_pack: item %d: all items need the same square filter (%d)", k, fw);
-        if ((int64_t)(it.out_h + fw - 1) * (it.out_w + fw - 1) >= (int64_t)1 << 31)
-            return set_error(GT_E_INVAL, "gt_batch_pack: item %d too large", k);
-        const int64_t tx = (it.out_w + ox - 1) / ox, ty = (it.out_h + oy - 1) / oy;
-        d[k].in = static_cast<const float *>(it.d_in);
-        d[k].w = static_cast<const float *>(it.d_filt);
-        d[k].out = static_cast<float *>(it.d_out);
-        d[k].out_h = it.out_h;
-        d[k].out_w = it.out_w;
-        d[k].tiles_x = (int32_t)tx;
-        d[k].flags = ((((uintptr_t)it.d_in & 15) == 0) ? 1 : 0) |
-                     (((((uintptr_t)it.d_out & 15) == 0) && it.out_w % 4 == 0) ? 2 : 0);
-        d[k].tile_begin = tiles;
-        tiles += tx * ty;
+        rc = fill_desc(items[k], k, fw, *cfg, &tiles, &d[k]);
+        if (rc) return rc;
     }
     *total_tiles = tiles;
     if (capacity < need) return set_error(GT_E_CAPACITY, "gt_batch_pack: %zu bytes needed", need);
@@ -167,36 +264,46 @@ int conv2d_run_batched(const void *d_blob, int32_t n_items, int64_t total_tiles,
     if ((uintptr_t)d_blob & 7) return set_error(GT_E_INVAL, "conv2d_run_batched: descriptor blob must be 8-byte aligned");
     int rc = validate_batch_config(*cfg, filt);
     if (rc) return rc;
-    const int64_t lds = batch_lds_bytes(*cfg, filt);
-    if (lds > state().dev.lds_per_block) return set_error(GT_E_UNSUPPORTED, "conv2d_run_batched: LDS tile too large");
-    const void *fn = batched_fn(cfg->tile_size_x, cfg->tile_size_y, filt);
-    if (lds > 65536) GT_HIP_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    const int threads = cfg->block_size_x * cfg->block_size_y;
-    int64_t grid;
-    if (grid_blocks <= 0) {
-        // The resident capacity; twice that for the VALU-bound filters (9 and
-        // up): workgroups beyond the resident ones start as others finish,
-        // which evens out the last round (measured +2-6 % for 17x17, while
-        // the HBM-bound 3x3 and 5x5 lose 2-3 % the same way, and a grid
-        // balanced to equal tiles per workgroup loses 10 % at 17x17).  A
-        // multiple of 8 for the per-XCD tile order.
-        int per_cu = 0;
-        GT_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, (size_t)lds));
-        const int64_t resident = (int64_t)std::max(1, per_cu) * std::max(1, state().dev.cu_count);
-        grid = std::min<int64_t>(total_tiles, (filt >= 9 ? 2 : 1) * resident);
-        if (grid >= 8) grid = grid / 8 * 8;
-    } else {
-        grid = std::min<int64_t>(grid_blocks, total_tiles);
+    return launch_batched(static_cast<const BatchDesc *>(d_blob), n_items, total_tiles, filt, *cfg, grid_blocks,
+                          (hipStream_t)hip_stream);
+}
+
+int conv2d_run_batched_noalloc(const gt_batch_item *items, int32_t n_items, const gt_conv_config *cfg,
+                               int32_t grid_blocks, void *hip_stream) {
+    clear_error();
+    if (!items || !cfg) return set_error(GT_E_INVAL, "conv2d_run_batched_noalloc: bad argument");
+    if (n_items < 1 || n_items > GT_BATCH_NOALLOC_MAX_ITEMS)
+        return set_error(GT_E_INVAL, "conv2d_run_batched_noalloc: %d items; 1 to %d fit the device descriptor array",
+                         n_items, GT_BATCH_NOALLOC_MAX_ITEMS);
+    if (!state().inited || (state().flags & GT_INIT_HOST_ONLY))
+        return set_error(GT_E_STATE, "conv2d_run_batched_noalloc: needs gt_init on a device");
+    const int fw = items[0].filt_w;
+    int rc = validate_batch_config(*cfg, fw);
+    if (rc) return rc;
+    // every item is checked before anything is issued
+    int64_t tiles = 0;
+    for (int32_t k = 0; k < n_items; ++k) {
+        BatchDesc d;
+        rc = fill_desc(items[k], k, fw, *cfg, &tiles, &d);
+        if (rc) return rc;
     }
-    const int pitch = (int)((cfg->block_size_x * cfg->tile_size_x + filt - 1 + 3) / 4 * 4 +
-                            4 * (cfg->use_lds_padding ? 1 : 0));
-    const BatchDesc *desc = static_cast<const BatchDesc *>(d_blob);
-    int n = n_items;
-    int64_t tt = total_tiles;
-    void *args[] = {&desc, &n, &tt, (void *)&pitch};
-    GT_HIP_CHECK(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(cfg->block_size_x, cfg->block_size_y), args,
-                                 (size_t)lds, (hipStream_t)hip_stream));
-    return GT_OK;
+    if (batch_lds_bytes(*cfg, fw) > state().dev.lds_per_block)
+        return set_error(GT_E_UNSUPPORTED, "conv2d_run_batched_noalloc: LDS tile too large");
+    BatchDesc *dev_desc = nullptr;
+    rc = scratch_ptr(&dev_desc);
+    if (rc) return rc;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    tiles = 0;
+    for (int32_t k0 = 0; k0 < n_items; k0 += kUploadChunk) {
+        DescChunk chunk;
+        memset(&chunk, 0, sizeof chunk);
+        chunk.first = k0;
+        chunk.n = std::min(kUploadChunk, n_items - k0);
+        for (int i = 0; i < chunk.n; ++i) fill_desc(items[k0 + i], k0 + i, fw, *cfg, &tiles, &chunk.d[i]);
+        hipLaunchKernelGGL(batch_desc_upload_kernel, dim3(1), dim3(64), 0, stream, dev_desc, chunk);
+        GT_HIP_CHECK(hipGetLastError());
+    }
+    return launch_batched(dev_desc, n_items, tiles, fw, *cfg, grid_blocks, stream);
 }
 
 // ---- graph capture of a launch sequence ----
