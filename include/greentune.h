@@ -101,6 +101,10 @@ typedef struct {
     double sample_period_ms;  /* sensor poll period; <= 0 -> 1.0 */
     int32_t min_launches;     /* at least this many launches; <= 0 -> 10 */
     int32_t warmup_launches;  /* untimed launches first; < 0 -> 3 */
+    int32_t use_graph;        /* 1: capture a group of launches into a HIP graph once and replay it
+                               * for the window (no host launch gaps between short kernels; the
+                               * group is as many launches as take about 1 ms, at most 256);
+                               * 0: launch one by one */
 } gt_measure_opts;
 
 /* One measurement (section III.B observer fields; section III.C metrics). */
@@ -134,6 +138,14 @@ typedef struct {
 typedef struct {
     double p_idle, alpha, beta, tau_mhz, p_max;
     double rss;               /* residual sum of squares of the fit, W^2 */
+    /* Covariance of the fitted parameters, row-major 4 x 4 in the order
+     * (p_idle W, alpha W/MHz, beta 1/MHz, tau_mhz MHz): s^2 (J^T J)^-1 at the
+     * solution, J the Jacobian of the modelled power over the free parameters
+     * (readings clipped at p_max contribute nothing), s^2 = rss / (n - k) for
+     * n readings and k free parameters (4, or 2 -- p_idle and alpha -- with
+     * measured voltage).  NaN where undefined: parameters not fitted, n <= k,
+     * or J^T J singular (e.g. beta = 0 leaves tau without influence). */
+    double cov[16];
     int32_t v_measured, literal_eq3, iters, status;  /* status 0 = converged */
 } gt_power_model;
 
@@ -372,6 +384,17 @@ int gt_batch_pack(const gt_batch_item *items, int32_t n_items, const gt_conv_con
  * captured in a graph.  Errors: GT_E_INVAL, GT_E_UNSUPPORTED, GT_E_HIP. */
 int conv2d_run_batched(const void *d_blob, int32_t n_items, int64_t total_tiles, int32_t filt,
                        const gt_conv_config *cfg, int32_t grid_blocks, void *hip_stream);
+
+/* measure_time_energy for a packed batch (sections III.A-III.B applied to
+ * the batched launch, for the per-size autotuner's energy objective): the
+ * launch of conv2d_run_batched with these arguments is repeated for the
+ * window.  flops_per_launch: the batch's algorithmic flops (the sum of
+ * gt_problem_flops over its items), from which rec->gflops and
+ * rec->gflops_per_w are derived.  Errors: as conv2d_run_batched and
+ * measure_time_energy. */
+int measure_batched_time_energy(const void *d_blob, int32_t n_items, int64_t total_tiles, int32_t filt,
+                                const gt_conv_config *cfg, int32_t grid_blocks, double flops_per_launch,
+                                gt_clock clock, const gt_measure_opts *opts, void *hip_stream, gt_measurement *rec);
 
 /* For callers that cannot allocate device memory (code under graph capture,
  * tight serving loops, harnesses that forbid hipMalloc): conv2d_run_batched

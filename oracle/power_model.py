@@ -150,8 +150,9 @@ def fit(f, p, p_max, v=None, literal=False, n_beta=161, n_tau=161):
                     p_max=float(p_max), sse=float(r @ r))
     fmin, fmax = float(f.min()), float(f.max())
     span = max(fmax - fmin, 1e-9)
-    # beta grid: voltage at f_max between 1x and 3x of its floor value
-    betas = np.concatenate([[0.0], np.geomspace(1e-4, 2.0, n_beta - 1)]) / span
+    # beta grid: Eq. 3 bounds beta only below (beta >= 0), so the grid spans
+    # voltage at f_max from 1x up to 21x of its floor value
+    betas = np.concatenate([[0.0], np.geomspace(1e-4, 20.0, n_beta - 1)]) / span
     taus = np.linspace(fmin, fmax, n_tau)
     cands = []
     for b in betas:
@@ -183,3 +184,54 @@ def fit(f, p, p_max, v=None, literal=False, n_beta=161, n_tau=161):
     s, pi, al, b, t = best
     return dict(p_idle=float(pi), alpha=float(al), beta=float(b), tau=float(t),
                 p_max=float(p_max), sse=float(s))
+
+
+def jacobian(f, p_idle, alpha, beta, tau, p_max, v=None, literal=False):
+    """Derivatives of Eq. 2 (with Eq. 3 unless measured voltage ``v`` is
+    given) with respect to (P_idle, alpha, beta, tau) at the clocks f, one
+    row per clock.  Where the model is clipped at P_max the row is zero (the
+    clipped power does not depend on the parameters).  With v given, beta and
+    tau have no influence (zero columns)."""
+    f = np.asarray(f, dtype=np.float64)
+    vv = voltage(f, beta, tau, literal) if v is None else np.asarray(v, dtype=np.float64)
+    unclipped = p_idle + alpha * f * vv * vv < p_max
+    above = (f >= tau) if v is None else np.zeros_like(f, dtype=bool)
+    # P = P_idle + alpha f v^2; both forms of Eq. 3 have dv/dbeta = f - tau
+    # and dv/dtau = -beta above tau (and v does not depend on them below)
+    j = np.zeros((f.size, 4))
+    j[:, 0] = 1.0
+    j[:, 1] = f * vv * vv
+    j[:, 2] = np.where(above, 2.0 * alpha * f * vv * (f - tau), 0.0)
+    j[:, 3] = np.where(above, -2.0 * alpha * f * vv * beta, 0.0)
+    j[~unclipped] = 0.0
+    return j
+
+
+def covariance(f, p, model, v=None):
+    """Covariance of the fitted parameters (P_idle, alpha, beta, tau) of a
+    least-squares fit: s^2 (J^T J)^-1 over the free parameters (all four, or
+    P_idle and alpha with measured voltage) at the fitted model, with
+    s^2 = SSE / (n - k) for n readings and k free parameters, the usual
+    linearised estimate for non-linear least squares.  NaN (4 x 4) entries
+    where undefined: parameters not fitted, n <= k, or J^T J singular."""
+    f = np.asarray(f, dtype=np.float64)
+    p = np.asarray(p, dtype=np.float64)
+    k = 2 if v is not None else 4
+    out = np.full((4, 4), np.nan)
+    if f.size <= k:
+        return out
+    args = (model["p_idle"], model["alpha"], model["beta"], model["tau"], model["p_max"])
+    j = jacobian(f, *args, v=v, literal=model.get("literal", False))[:, :k]
+    a = j.T @ j
+    # conditioning judged on the equilibrated matrix (unit diagonal), which
+    # does not depend on the units of the parameters
+    d = np.sqrt(np.diag(a))
+    if not np.all(np.isfinite(a)) or not np.all(d > 0):
+        return out
+    ae = a / np.outer(d, d)
+    if np.linalg.cond(ae) > 1e12:
+        return out
+    r = p - power(f, *args, v=v, literal=model.get("literal", False))
+    s2 = float(r @ r) / (f.size - k)
+    out[:k, :k] = s2 * np.linalg.inv(ae) / np.outer(d, d)
+    return out

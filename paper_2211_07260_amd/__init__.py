@@ -67,7 +67,7 @@ class DvfsBackend(ctypes.Structure):
 class MeasureOpts(ctypes.Structure):
     _fields_ = [("window_s", ctypes.c_double), ("discard_s", ctypes.c_double),
                 ("sample_period_ms", ctypes.c_double), ("min_launches", ctypes.c_int32),
-                ("warmup_launches", ctypes.c_int32)]
+                ("warmup_launches", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
 _MEAS_D = ("t_run_s", "p_median_w", "p_min_w", "p_max_w", "e_run_j", "e_run_counter_j", "gflops",
@@ -85,10 +85,17 @@ class Measurement(ctypes.Structure):
 
 class PowerModel(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in ("p_idle", "alpha", "beta", "tau_mhz", "p_max", "rss")] + \
+               [("cov", ctypes.c_double * 16)] + \
                [(n, ctypes.c_int32) for n in ("v_measured", "literal_eq3", "iters", "status")]
 
+    def covariance(self):
+        """4 x 4 covariance of (p_idle, alpha, beta, tau_mhz) as nested lists."""
+        return [[self.cov[4 * i + j] for j in range(4)] for i in range(4)]
+
     def as_dict(self):
-        return {n: getattr(self, n) for n, _ in self._fields_}
+        d = {n: getattr(self, n) for n, _ in self._fields_ if n != "cov"}
+        d["cov"] = self.covariance()
+        return d
 
 
 class BatchItem(ctypes.Structure):
@@ -164,6 +171,8 @@ def _load():
         "conv2d_run_batched": ([vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P(ConvConfig),
                                 ctypes.c_int32, vp], c_int),
         "conv2d_run_batched_noalloc": ([P(BatchItem), ctypes.c_int32, P(ConvConfig), ctypes.c_int32, vp], c_int),
+        "measure_batched_time_energy": ([vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P(ConvConfig),
+                                         ctypes.c_int32, c_double, Clock, P(MeasureOpts), vp, P(Measurement)], c_int),
         "gt_graph_begin": ([vp], c_int),
         "gt_graph_end": ([vp, P(vp)], c_int),
         "gt_graph_launch": ([vp, vp], c_int),
@@ -188,7 +197,7 @@ EXPORTED = ("gt_init", "gt_shutdown", "gt_last_error", "gt_version", "conv2d_run
             "gt_measure_last_window", "gt_problem_flops",
             "gt_conv_lds_bytes", "gt_sensor_read", "gt_settable_clocks", "gt_dvfs_state", "gt_power_cap_range", "gt_dvfs_set_backend", "gt_sensor_stale",
             "gt_fake_sensor_model", "gt_roofline_probe", "gt_mfma_probe", "gt_batch_pack", "conv2d_run_batched",
-            "conv2d_run_batched_noalloc",
+            "conv2d_run_batched_noalloc", "measure_batched_time_energy",
             "gt_graph_begin", "gt_graph_end", "gt_graph_launch", "gt_graph_destroy", "gt_sampler_start",
             "gt_sampler_stop", "gt_sensor_busy", "gt_ffg_centrality")
 
@@ -294,8 +303,8 @@ def tune_space_enumerate(problem, values, max_threads=0, lds_limit=0, dedup_dire
 
 
 def measure_time_energy(problem, cfg, inp, filt, out, clk=None, window_s=1.0, discard_s=0.3,
-                        sample_period_ms=1.0, min_launches=10, warmup_launches=3, stream=None):
-    o = MeasureOpts(window_s, discard_s, sample_period_ms, min_launches, warmup_launches)
+                        sample_period_ms=1.0, min_launches=10, warmup_launches=3, stream=None, use_graph=False):
+    o = MeasureOpts(window_s, discard_s, sample_period_ms, min_launches, warmup_launches, 1 if use_graph else 0)
     m = Measurement()
     _check(_lib.measure_time_energy(ctypes.byref(problem), ctypes.byref(as_config(cfg)), clk or clock(),
                                     ctypes.byref(o), _ptr(inp), _ptr(filt), _ptr(out), _stream(stream),
@@ -541,6 +550,20 @@ class Batch:
     def run(self, grid_blocks=0, stream=None):
         _check(_lib.conv2d_run_batched(_ptr(self.blob), self.n, self.total_tiles, self.filt, ctypes.byref(self.cfg),
                                        grid_blocks, _stream(stream)))
+
+    def flops(self):
+        return sum(2.0 * oh * ow * f * f for (_, _, _, oh, ow, f) in self._keep)
+
+    def measure(self, clk=None, window_s=1.0, discard_s=0.3, sample_period_ms=1.0, min_launches=10,
+                warmup_launches=3, grid_blocks=0, stream=None, use_graph=False):
+        """measure_batched_time_energy of this batch: time and energy per
+        launch of the whole batch over a window."""
+        o = MeasureOpts(window_s, discard_s, sample_period_ms, min_launches, warmup_launches, 1 if use_graph else 0)
+        m = Measurement()
+        _check(_lib.measure_batched_time_energy(_ptr(self.blob), self.n, self.total_tiles, self.filt,
+                                                ctypes.byref(self.cfg), int(grid_blocks), self.flops(),
+                                                clk or clock(), ctypes.byref(o), _stream(stream), ctypes.byref(m)))
+        return m.as_dict()
 
 
 BATCH_NOALLOC_MAX_ITEMS = 4096

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -70,6 +71,12 @@ int dvfs_settable(double step_mhz, std::vector<double> &out);
 double dvfs_requested_mhz();             // 0 when the clock is at its default
 
 double now_s();                          // host steady clock
+
+// The measurement window of measure_time_energy (measure.cpp): warm-up,
+// launches back to back (or graph replays) for the window while the sampler
+// runs, time from HIP events, energy by gt_energy_from_samples.
+int measure_window(const std::function<int(hipStream_t)> &launch, double flops_per_launch, gt_measure_opts o,
+                   hipStream_t s, gt_measurement *rec);
 
 // ---- method arithmetic (host, FP64) ----
 double median_of(std::vector<double> v);

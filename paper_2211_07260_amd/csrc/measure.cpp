@@ -27,6 +27,17 @@ struct EventPair {
     }
 };
 
+// A captured group of launches (use_graph), and the library stream it runs
+// on when the caller passed the null stream (which cannot be captured).
+struct GraphGroup {
+    hipGraphExec_t exec = nullptr;
+    hipStream_t own = nullptr;
+    ~GraphGroup() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (own) (void)hipStreamDestroy(own);
+    }
+};
+
 // The readings of the most recent measurement window (gt_measure_last_window).
 struct LastWindow {
     std::mutex mu;
@@ -90,7 +101,40 @@ int measure_window(const std::function<int(hipStream_t)> &launch, double flops_p
     float est_ms = 0;
     GT_HIP_CHECK(hipEventElapsedTime(&est_ms, est.a, est.b));
     const double t_est = std::max(1e-7, est_ms * 1e-3 / 3.0);
-    const int64_t n = std::max<int64_t>(o.min_launches, (int64_t)std::ceil(o.window_s / t_est));
+    int64_t n = std::max<int64_t>(o.min_launches, (int64_t)std::ceil(o.window_s / t_est));
+
+    // use_graph: capture `group` launches once (about 1 ms of work, at most
+    // 256) and replay the graph for the window; the caller's null stream is
+    // replaced by a library stream after the work queued on it has finished.
+    GraphGroup gg;
+    int64_t group = 1;
+    if (o.use_graph) {
+        group = std::min<int64_t>(256, std::max<int64_t>(1, (int64_t)std::ceil(1e-3 / t_est)));
+        if (!s) {
+            GT_HIP_CHECK(hipStreamSynchronize(s));
+            GT_HIP_CHECK(hipStreamCreateWithFlags(&gg.own, hipStreamNonBlocking));
+            s = gg.own;
+        }
+        hipGraph_t g = nullptr;
+        GT_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        for (int64_t k = 0; k < group && rc == GT_OK; ++k) rc = launch(s);
+        const hipError_t ce = hipStreamEndCapture(s, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (ce != hipSuccess) return set_error(GT_E_HIP, "measure: graph capture: %s", hipGetErrorString(ce));
+        const hipError_t ie = hipGraphInstantiate(&gg.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) return set_error(GT_E_HIP, "measure: graph instantiate: %s", hipGetErrorString(ie));
+        GT_HIP_CHECK(hipGraphLaunch(gg.exec, s));  // one untimed replay
+        n = (n + group - 1) / group * group;
+    }
+    auto issue = [&](hipStream_t st) -> int {
+        if (!gg.exec) return launch(st);
+        const hipError_t e = hipGraphLaunch(gg.exec, st);
+        return e == hipSuccess ? GT_OK : set_error(GT_E_HIP, "measure: graph launch: %s", hipGetErrorString(e));
+    };
 
     std::vector<gt_sensor_sample> samples;
     samples.reserve((size_t)(o.window_s * 1000.0 / o.sample_period_ms) + 64);
@@ -111,8 +155,8 @@ int measure_window(const std::function<int(hipStream_t)> &launch, double flops_p
     const double t_start = now_s();
     hipError_t herr = hipEventRecord(win.a, s);
     int64_t launched = 0;
-    for (; launched < n && herr == hipSuccess; ++launched) {
-        rc = launch(s);
+    for (; launched < n && herr == hipSuccess; launched += group) {
+        rc = issue(s);
         if (rc) break;
     }
     if (herr == hipSuccess && rc == GT_OK) herr = hipEventRecord(win.b, s);
@@ -271,7 +315,7 @@ extern "C" int measure_time_energy(const gt_problem *problem, const gt_conv_conf
     if (!state().inited) return set_error(GT_E_STATE, "measure_time_energy: call gt_init first");
     if (state().flags & GT_INIT_HOST_ONLY)
         return set_error(GT_E_STATE, "measure_time_energy: library initialised host-only");
-    const gt_measure_opts o = opts ? *opts : gt_measure_opts{0, -1, 0, 0, -1};
+    const gt_measure_opts o = opts ? *opts : gt_measure_opts{0, -1, 0, 0, -1, 0};
     if (o.window_s > 0 && o.discard_s >= o.window_s)
         return set_error(GT_E_INVAL, "measure_time_energy: discard %.3f s >= window %.3f s", o.discard_s,
                          o.window_s);
@@ -294,7 +338,7 @@ extern "C" int measure_load(int32_t kind, gt_clock clock, const gt_measure_opts 
     if (rc) return rc;
     rc = dvfs_apply(clock);
     if (rc) return rc;
-    const gt_measure_opts o = opts ? *opts : gt_measure_opts{0, -1, 0, 0, -1};
+    const gt_measure_opts o = opts ? *opts : gt_measure_opts{0, -1, 0, 0, -1, 0};
     return measure_window([&](hipStream_t s) { return launch_load(kind, d_buf, bytes, s); }, work, o,
                           (hipStream_t)hip_stream, rec);
 }

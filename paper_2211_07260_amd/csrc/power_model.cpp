@@ -209,6 +209,63 @@ LmResult lm(const Data &d, const double th0[4], int k, double t_lo, double t_hi)
     return R;
 }
 
+// Covariance of the fitted parameters: s^2 (J^T J)^-1 over the k free
+// parameters at th (internal units), s^2 = sse / (n - k); written into
+// cov[16] (public units, row-major (p_idle, alpha, beta, tau)), NaN where
+// undefined.  Readings clipped at p_max have a zero Jacobian row, as in lm().
+void covariance(const Data &d, const double th[4], int k, double sse, double cov[16]) {
+    for (int i = 0; i < 16; ++i) cov[i] = NAN;
+    if ((int)d.n <= k) return;
+    double A[4][4] = {{0}};
+    for (size_t i = 0; i < d.n; ++i) {
+        const double x = d.x[i];
+        const double vv = d.v ? d.v[i] : volt(x, th[2], th[3], d.literal);
+        if (th[0] + th[1] * x * vv * vv >= d.p_max) continue;
+        double Ji[4];
+        Ji[0] = 1.0;
+        Ji[1] = x * vv * vv;
+        const bool above = !d.v && x >= th[3];
+        Ji[2] = above ? 2.0 * th[1] * x * vv * (x - th[3]) : 0.0;  // dv/db = x - t in both forms of Eq. 3
+        Ji[3] = above ? -2.0 * th[1] * x * vv * th[2] : 0.0;
+        for (int p = 0; p < k; ++p)
+            for (int q = 0; q < k; ++q) A[p][q] += Ji[p] * Ji[q];
+    }
+    // equilibrate (unit diagonal: the conditioning then does not depend on
+    // the parameters' units), invert by solving A z = e_j, and leave NaN for
+    // a singular or ill-conditioned matrix (max-abs norms of A and A^-1,
+    // product beyond 1e12)
+    double dg[4];
+    for (int p = 0; p < k; ++p) {
+        dg[p] = std::sqrt(A[p][p]);
+        if (!(dg[p] > 0) || !std::isfinite(dg[p])) return;
+    }
+    for (int p = 0; p < k; ++p)
+        for (int q = 0; q < k; ++q) A[p][q] /= dg[p] * dg[q];
+    double inv[4][4];
+    for (int j = 0; j < k; ++j) {
+        double A2[4][4], e[4] = {0, 0, 0, 0}, z[4] = {0, 0, 0, 0};
+        for (int p = 0; p < k; ++p)
+            for (int q = 0; q < k; ++q) A2[p][q] = A[p][q];
+        e[j] = 1.0;
+        if (!solve(k, A2, e, z)) return;
+        for (int p = 0; p < k; ++p) inv[p][j] = z[p];
+    }
+    double imax = 0, amax = 0;
+    for (int p = 0; p < k; ++p)
+        for (int q = 0; q < k; ++q) {
+            imax = std::max(imax, std::fabs(inv[p][q]));
+            amax = std::max(amax, std::fabs(A[p][q]));
+        }
+    if (!(amax * imax < 1e12)) return;
+    for (int p = 0; p < k; ++p)
+        for (int q = 0; q < k; ++q) inv[p][q] /= dg[p] * dg[q];
+    const double s2 = sse / (double)((int)d.n - k);
+    // internal -> public units: alpha = a / 1000, beta = b / 1000, tau = 1000 t
+    const double scale[4] = {1.0, 1e-3, 1e-3, 1e3};
+    for (int p = 0; p < k; ++p)
+        for (int q = 0; q < k; ++q) cov[p * 4 + q] = s2 * inv[p][q] * scale[p] * scale[q];
+}
+
 }  // namespace
 }  // namespace gt
 
@@ -273,6 +330,7 @@ int fit_power_model(const double *f_mhz, const double *p_w, const double *v_or_n
     out->literal_eq3 = literal ? 1 : 0;
     out->iters = best.iters;
     out->status = best.status;
+    covariance(d, best.th, v_or_null ? 2 : 4, best.sse, out->cov);
     return GT_OK;
 }
 

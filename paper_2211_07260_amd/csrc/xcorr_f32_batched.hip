@@ -306,6 +306,31 @@ int conv2d_run_batched_noalloc(const gt_batch_item *items, int32_t n_items, cons
     return launch_batched(dev_desc, n_items, tiles, fw, *cfg, grid_blocks, stream);
 }
 
+int measure_batched_time_energy(const void *d_blob, int32_t n_items, int64_t total_tiles, int32_t filt,
+                                const gt_conv_config *cfg, int32_t grid_blocks, double flops_per_launch,
+                                gt_clock clock, const gt_measure_opts *opts, void *hip_stream, gt_measurement *rec) {
+    clear_error();
+    if (!d_blob || n_items < 1 || total_tiles < 1 || !cfg || !rec || !(flops_per_launch > 0))
+        return set_error(GT_E_INVAL, "measure_batched_time_energy: bad argument");
+    if (!state().inited || (state().flags & GT_INIT_HOST_ONLY))
+        return set_error(GT_E_STATE, "measure_batched_time_energy: needs gt_init on a device");
+    if ((uintptr_t)d_blob & 7)
+        return set_error(GT_E_INVAL, "measure_batched_time_energy: descriptor blob must be 8-byte aligned");
+    int rc = validate_batch_config(*cfg, filt);
+    if (rc) return rc;
+    const gt_measure_opts o = opts ? *opts : gt_measure_opts{0, -1, 0, 0, -1, 0};
+    if (o.window_s > 0 && o.discard_s >= o.window_s)
+        return set_error(GT_E_INVAL, "measure_batched_time_energy: discard %.3f s >= window %.3f s", o.discard_s,
+                         o.window_s);
+    rc = dvfs_apply(clock);
+    if (rc) return rc;
+    const BatchDesc *desc = static_cast<const BatchDesc *>(d_blob);
+    const gt_conv_config c = *cfg;
+    return measure_window(
+        [&](hipStream_t s) { return launch_batched(desc, n_items, total_tiles, filt, c, grid_blocks, s); },
+        flops_per_launch, o, (hipStream_t)hip_stream, rec);
+}
+
 // ---- graph capture of a launch sequence ----
 
 int gt_graph_begin(void *hip_stream) {

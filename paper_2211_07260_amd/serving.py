@@ -132,12 +132,17 @@ class Engine:
     a BF16 request of more than part_flops runs on its own stream in parts
     of about part_flops each, at most parts_ahead of them queued, so that
     short work issued meanwhile starts after the running part instead of
-    after the whole request (part_flops=None: no parts)."""
+    after the whole request (part_flops=None: no parts).  objective: which
+    per-size config of the autotuner's store the batched launches use
+    ("time" or "energy")."""
 
     def __init__(self, mem_budget=32 << 30, max_slots=512, max_batch=256, n_streams=2, store=None,
                  keep_outputs=False, device="cuda:0", streams=None, long_stream=None, part_flops=1.0e12,
-                 parts_ahead=2):
+                 parts_ahead=2, objective="time"):
         import torch
+        if objective not in autotune.OBJECTIVES:
+            raise ValueError("objective must be one of %s" % (autotune.OBJECTIVES,))
+        self.objective = objective
         self.torch = torch
         self.device = torch.device(device)
         self.mem_budget, self.max_slots, self.max_batch = mem_budget, max_slots, max_batch
@@ -217,7 +222,7 @@ class Engine:
             for f, rs in groups.items():
                 # config of the group's typical size (work-weighted mean side)
                 side = math.sqrt(sum(r.side ** 2 for r in rs) / len(rs))
-                cfg = autotune.lookup(self.store, f, side)
+                cfg = autotune.lookup(self.store, f, side, self.objective)
                 for r in rs:
                     r.config = cfg
                 b = gt.Batch([(r.bufs[0], r.bufs[1], r.bufs[2], r.side, r.side, f) for r in rs], cfg)

@@ -317,3 +317,36 @@ def test_window_clock_skips_invalid_timestamps_and_clocks():
              _smp(0.4, 1900.0, 3.0)]
     f, n = gt.window_clock(trace, 0.05, 1.0)
     assert n == 1 and f == 1800.0  # 2.0 carries no clock, 3.0 counts once
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_fit_covariance_matches_oracle(seed):
+    # s^2 (J^T J)^-1 at the fitted parameters: the library's (from its own
+    # fit) against the oracle's (from the oracle's fit of the same readings)
+    rng = np.random.default_rng(100 + seed)
+    m = dict(p_idle=rng.uniform(100, 300), alpha=rng.uniform(0.05, 0.3), beta=rng.uniform(0.0005, 0.002),
+             tau=rng.uniform(900, 1500), p_max=1e9)
+    f = np.linspace(500.0, 2400.0, 7)
+    p = _synth(f, m) + rng.normal(0, 3.0, f.size)
+    r = gt.fit_power_model(f, p, m["p_max"])
+    o = opm.fit(f, p, m["p_max"])
+    assert r.rss == pytest.approx(o["sse"], rel=1e-6)
+    co = opm.covariance(f, p, o)
+    cr = np.array(r.covariance())
+    assert np.all(np.isfinite(co)) and np.all(np.isfinite(cr))
+    assert np.allclose(cr, co, rtol=2e-3, atol=0), (cr, co)
+
+
+def test_fit_covariance_measured_voltage_and_undefined():
+    f = np.array([600.0, 1000.0, 1400.0, 1800.0, 2200.0])
+    v = np.array([0.70, 0.72, 0.80, 0.92, 1.05])
+    p = 120.0 + 0.3 * f * v * v + np.array([2.0, -3.0, 1.0, 4.0, -2.5])
+    r = gt.fit_power_model(f, p, 1e9, v=v)
+    o = opm.fit(f, p, 1e9, v=v)
+    cr, co = np.array(r.covariance()), opm.covariance(f, p, o, v=v)
+    assert np.allclose(cr[:2, :2], co[:2, :2], rtol=1e-8)
+    assert np.all(np.isnan(cr[2:, :])) and np.all(np.isnan(cr[:, 2:]))
+    # four readings for four parameters: no degrees of freedom left
+    r4 = gt.fit_power_model(f[:4], p[:4] * 0 + _synth(f[:4], dict(p_idle=150, alpha=0.2, beta=1e-3, tau=1100,
+                                                                   p_max=1e9)), 1e9)
+    assert np.all(np.isnan(np.array(r4.covariance())))

@@ -198,3 +198,70 @@ def test_fit_with_measured_voltage_is_linear_least_squares():
     r = pm.fit(f, p, 1e9, v=v)
     assert r["p_idle"] == pytest.approx(120.0, rel=1e-9)
     assert r["alpha"] == pytest.approx(0.3, rel=1e-9)
+
+
+# ---- covariance of the fitted parameters ----
+
+def test_covariance_measured_voltage_is_simple_regression():
+    # with measured voltage Eq. 2 is P = P_idle + alpha * g, g = f v^2: the
+    # covariance is that of simple linear regression, whose textbook scalar
+    # forms are var(slope) = s^2 / Sxx, var(intercept) = s^2 (1/n + gbar^2 /
+    # Sxx), cov = -gbar s^2 / Sxx, with Sxx = sum (g - gbar)^2
+    rng = np.random.default_rng(3)
+    f = np.array([600.0, 1000.0, 1400.0, 1800.0, 2200.0])
+    v = np.array([0.70, 0.72, 0.80, 0.92, 1.05])
+    p = 120.0 + 0.3 * f * v * v + rng.normal(0, 5.0, f.size)
+    m = pm.fit(f, p, 1e9, v=v)
+    c = pm.covariance(f, p, m, v=v)
+    g = f * v * v
+    n = f.size
+    gbar = g.mean()
+    sxx = float(((g - gbar) ** 2).sum())
+    resid = p - (m["p_idle"] + m["alpha"] * g)
+    s2 = float((resid ** 2).sum()) / (n - 2)
+    assert c[1, 1] == pytest.approx(s2 / sxx, rel=1e-9)
+    assert c[0, 0] == pytest.approx(s2 * (1.0 / n + gbar * gbar / sxx), rel=1e-9)
+    assert c[0, 1] == pytest.approx(-gbar * s2 / sxx, rel=1e-9)
+    assert c[1, 0] == c[0, 1]
+    assert np.all(np.isnan(c[2:, :])) and np.all(np.isnan(c[:, 2:]))
+
+
+@pytest.mark.parametrize("literal", [False, True])
+def test_jacobian_matches_finite_differences(literal):
+    # the analytic derivatives against central differences of Eq. 2/3 itself,
+    # away from tau (where v has a kink) and from the P_max clip
+    rng = np.random.default_rng(11 + literal)
+    for _ in range(20):
+        th = np.array([rng.uniform(50, 300), rng.uniform(0.05, 0.4), rng.uniform(2e-4, 2e-3),
+                       rng.uniform(900, 1600)])
+        f = np.array([600.0, 800.0, 1750.0, 2000.0, 2300.0])
+        f = f[np.abs(f - th[3]) > 20.0]
+        j = pm.jacobian(f, *th, 1e12, literal=literal)
+        for q in range(4):
+            h = 1e-6 * max(abs(th[q]), 1e-3)
+            hi, lo = th.copy(), th.copy()
+            hi[q] += h
+            lo[q] -= h
+            fd = (pm.power(f, *hi, 1e12, literal=literal) - pm.power(f, *lo, 1e12, literal=literal)) / (2 * h)
+            assert np.allclose(j[:, q], fd, rtol=1e-6, atol=1e-9 * np.abs(fd).max() + 1e-12), (q, j[:, q], fd)
+
+
+def test_jacobian_zero_where_clipped():
+    f = np.array([500.0, 1500.0, 2400.0])
+    j = pm.jacobian(f, 200.0, 0.5, 1e-3, 1000.0, 900.0)
+    unclipped = 200.0 + 0.5 * f * pm.voltage(f, 1e-3, 1000.0) ** 2 < 900.0
+    assert unclipped.tolist() == [True, False, False]
+    assert np.all(j[~unclipped] == 0.0) and np.all(j[0, :2] != 0.0)
+
+
+def test_covariance_undefined_cases():
+    f = np.array([600.0, 1000.0, 1500.0, 2100.0])
+    m = dict(p_idle=150.0, alpha=0.2, beta=1e-3, tau=1200.0, p_max=1e9)
+    p = pm.power(f, m["p_idle"], m["alpha"], m["beta"], m["tau"], m["p_max"]) + np.array([1.0, -2.0, 0.5, 1.5])
+    assert np.all(np.isnan(pm.covariance(f, p, m)))          # n = k = 4: no degrees of freedom
+    f5 = np.append(f, 2400.0)
+    p5 = np.append(p, 700.0)
+    m0 = dict(m, beta=0.0)                                      # beta = 0: tau has no influence
+    assert np.all(np.isnan(pm.covariance(f5, p5, m0)))
+    c = pm.covariance(f5, p5, m)
+    assert np.all(np.isfinite(c)) and np.all(np.diag(c) > 0) and np.allclose(c, c.T, rtol=1e-9)
