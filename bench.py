@@ -112,11 +112,12 @@ def cpu_baseline(img, w, gpu_out=None):
     return res
 
 
-def igemm_extras(gt, torch, dev, steps=20, energy=True, outputs=None):
+def igemm_extras(gt, torch, dev, steps=200, energy=True, outputs=None, warmup_s=0.3):
     """Multi-channel conv (N=16, C_in=C_out=64, 128x128, same padding), BF16
-    MFMA and FP32 VALU paths on the same BF16-valued data: ms, TFLOP/s and
-    (measured with measure_time_energy) GFLOP/s/W.  Host copies of the
-    outputs go to `outputs` (for the error against the oracle)."""
+    MFMA and FP32 VALU paths on the same BF16-valued data: ms, TFLOP/s (after
+    warmup_s of launches, as for the headline kernel) and (measured with
+    measure_time_energy) GFLOP/s/W.  Host copies of the outputs go to
+    `outputs` (for the error against the oracle)."""
     from synthetic import conv_inputs
     res = {}
     for f in (3, 5):
@@ -126,8 +127,11 @@ def igemm_extras(gt, torch, dev, steps=20, energy=True, outputs=None):
                                    (gt.IGEMM_F32_VALU, "f32_valu", x.float(), wt.float())):
             dx, dw = xx.to(dev).contiguous(), ww.to(dev).contiguous()
             p = gt.conv_problem(kind, 16, 128, 128, 64, 64, f, f)
-            for _ in range(3):
-                gt.conv2d_run(p, (64, 1, 1, 1, 0, 0), dx, dw, out)
+            t_w0 = time.perf_counter()
+            while time.perf_counter() - t_w0 < warmup_s:
+                for _ in range(10):
+                    gt.conv2d_run(p, (64, 1, 1, 1, 0, 0), dx, dw, out)
+                torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
             for _ in range(steps):
@@ -332,6 +336,23 @@ def main():
                      "traffic": traffic},
     }
     result.update(synthetic_loads=loads, multichannel=extras, serving=serving_rep)
+    gain = (energy or {}).get("efficiency_gain_energy_vs_time")
+    result["targets"] = {
+        "energy_tuned_vs_time_tuned_gflops_per_w": {
+            "target": 1.3, "measured": gain, "met": bool(gain is not None and gain >= 1.3),
+            "note": "measured in this run at the default clock, over configurations only: the clock knob needs a "
+                    "DVFS backend, which this host does not permit (the library refuses with GT_E_PERM)"},
+        "fp32_roofline_frac": {
+            "target": 0.5, "measured": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+            "met": achieved / FP32_VECTOR_PEAK_TFLOPS >= 0.5,
+            "note": "of the 157.3 TFLOP/s published peak, which counts packed FP32 FMA; packed FP32 is disabled "
+                    "in this build, so the one-FMA-per-lane ceiling is 78.6 TFLOP/s = 0.5 of it "
+                    "(frac_of_nonpacked_peak under roofline)"},
+        "clock_points_fewer_than_full_sweep": {
+            "target": 5.0, "measured": None, "met": None,
+            "note": "not measurable on this host (no clock changes permitted); the steered search reaches >= 5x "
+                    "fewer points than the exhaustive sweep on a simulated device in the host tests"},
+    }
     if tuned:
         result["stored_sweep"] = dict(
             source="the committed sweep of the tune space (paper_2211_07260_amd/tuned/), measured on MI355X "

@@ -415,6 +415,29 @@ int measure_batched_time_energy(const void *d_blob, int32_t n_items, int64_t tot
 int conv2d_run_batched_noalloc(const gt_batch_item *items, int32_t n_items, const gt_conv_config *cfg,
                                int32_t grid_blocks, void *hip_stream);
 
+/* Batching for multi-channel BF16 convolutions (the MFMA kind): many
+ * convolutions of one shape family -- shared c_in, c_out, square filter and
+ * padding, given by `shape` (its n, out_h, out_w are ignored) -- each of
+ * one image (n = 1) of its own size, in one persistent launch.  items: as
+ * for gt_batch_pack (d_in NHWC BF16 [H][W][c_in], d_filt KRSC BF16, d_out
+ * NHWC FP32 [out_h][out_w][c_out], H = out_h + filt - 1 - 2 pad), input and
+ * weights 16-byte aligned.  Packs 64-byte descriptors into host_blob, which
+ * the caller copies to device memory (8-byte aligned) for
+ * conv2d_run_igemm_batched; *blob_bytes and *total_blocks (workgroup blocks of
+ * 256 output pixels over all items) are always written, GT_E_CAPACITY if
+ * capacity is too small.  The launch runs the global-load MFMA kernel on
+ * every block (grid_blocks workgroups along the pixels, 0 = about the
+ * resident capacity); each output equals bit for bit what that kernel writes
+ * for the convolution alone (conv2d_run takes the LDS-staged kernel where it
+ * applies, which sums in another order; both agree within FP32 rounding).
+ * Launch only: no allocation, no memset.  Errors: GT_E_INVAL,
+ * GT_E_UNSUPPORTED (kind other than GT_IGEMM_BF16_MFMA, non-square filter,
+ * c_in not 32 or 64, c_out not a multiple of 32), GT_E_STATE, GT_E_HIP. */
+int gt_igemm_batch_pack(const gt_problem *shape, const gt_batch_item *items, int32_t n_items, void *host_blob,
+                        size_t capacity, size_t *blob_bytes, int64_t *total_blocks);
+int conv2d_run_igemm_batched(const gt_problem *shape, const void *d_blob, int32_t n_items, int64_t total_blocks,
+                             int32_t grid_blocks, void *hip_stream);
+
 /* Graph capture of the launches issued on hip_stream between begin and end
  * (hipStreamBeginCapture / EndCapture / Instantiate).  *graph_exec is an
  * opaque executable graph owned by the caller until gt_graph_destroy. */

@@ -171,6 +171,9 @@ def _load():
         "conv2d_run_batched": ([vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P(ConvConfig),
                                 ctypes.c_int32, vp], c_int),
         "conv2d_run_batched_noalloc": ([P(BatchItem), ctypes.c_int32, P(ConvConfig), ctypes.c_int32, vp], c_int),
+        "gt_igemm_batch_pack": ([P(Problem), P(BatchItem), ctypes.c_int32, vp, c_size, P(c_size),
+                                 P(ctypes.c_int64)], c_int),
+        "conv2d_run_igemm_batched": ([P(Problem), vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, vp], c_int),
         "measure_batched_time_energy": ([vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P(ConvConfig),
                                          ctypes.c_int32, c_double, Clock, P(MeasureOpts), vp, P(Measurement)], c_int),
         "gt_graph_begin": ([vp], c_int),
@@ -197,7 +200,8 @@ EXPORTED = ("gt_init", "gt_shutdown", "gt_last_error", "gt_version", "conv2d_run
             "gt_measure_last_window", "gt_problem_flops",
             "gt_conv_lds_bytes", "gt_sensor_read", "gt_settable_clocks", "gt_dvfs_state", "gt_power_cap_range", "gt_dvfs_set_backend", "gt_sensor_stale",
             "gt_fake_sensor_model", "gt_roofline_probe", "gt_mfma_probe", "gt_batch_pack", "conv2d_run_batched",
-            "conv2d_run_batched_noalloc", "measure_batched_time_energy",
+            "conv2d_run_batched_noalloc", "measure_batched_time_energy", "gt_igemm_batch_pack",
+            "conv2d_run_igemm_batched",
             "gt_graph_begin", "gt_graph_end", "gt_graph_launch", "gt_graph_destroy", "gt_sampler_start",
             "gt_sampler_stop", "gt_sensor_busy", "gt_ffg_centrality")
 
@@ -564,6 +568,43 @@ class Batch:
                                                 ctypes.byref(self.cfg), int(grid_blocks), self.flops(),
                                                 clk or clock(), ctypes.byref(o), _stream(stream), ctypes.byref(m)))
         return m.as_dict()
+
+
+class IgemmBatch:
+    """A packed batch of multi-channel BF16 convolutions of one shape family
+    (c_in, c_out, square filter f, padding pad; one image each).  convs: list
+    of (d_in, d_filt, d_out, out_h, out_w) with torch device tensors (NHWC
+    BF16 input, KRSC BF16 weights, NHWC FP32 output).  Descriptor upload as
+    for Batch."""
+
+    def __init__(self, convs, c_in, c_out, f, pad):
+        import torch
+        self.shape = conv_problem(IGEMM_BF16_MFMA, 1, 1, 1, c_in, c_out, f, f)
+        self.shape.pad_h = self.shape.pad_w = int(pad)
+        items = (BatchItem * len(convs))()
+        for k, (di, dw, do, oh, ow) in enumerate(convs):
+            items[k] = BatchItem(di.data_ptr(), dw.data_ptr(), do.data_ptr(), oh, ow, f, f)
+        self.n = len(convs)
+        nb, tb = ctypes.c_size_t(0), ctypes.c_int64(0)
+        rc = _lib.gt_igemm_batch_pack(ctypes.byref(self.shape), items, self.n, None, 0, ctypes.byref(nb),
+                                      ctypes.byref(tb))
+        if rc not in (GT_OK, GT_E_CAPACITY):
+            _check(rc)
+        self._host = torch.empty(nb.value, dtype=torch.uint8, pin_memory=True)
+        _check(_lib.gt_igemm_batch_pack(ctypes.byref(self.shape), items, self.n,
+                                        ctypes.c_void_p(self._host.data_ptr()), nb.value, ctypes.byref(nb),
+                                        ctypes.byref(tb)))
+        self.total_blocks = tb.value
+        self.blob = self._host.to(convs[0][0].device, non_blocking=True)
+        self._keep = convs
+
+    def flops(self):
+        c_in, c_out, f = self.shape.c_in, self.shape.c_out, self.shape.filt_h
+        return sum(2.0 * oh * ow * c_in * c_out * f * f for (_, _, _, oh, ow) in self._keep)
+
+    def run(self, grid_blocks=0, stream=None):
+        _check(_lib.conv2d_run_igemm_batched(ctypes.byref(self.shape), _ptr(self.blob), self.n, self.total_blocks,
+                                             int(grid_blocks), _stream(stream)))
 
 
 BATCH_NOALLOC_MAX_ITEMS = 4096

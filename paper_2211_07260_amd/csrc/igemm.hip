@@ -21,10 +21,12 @@
 //   GEMM (each thread 4 pixels x 4 output channels) over LDS-staged,
 //   channel-major slices of the input and the weights.
 #include <hip/hip_runtime.h>
+#include <string.h>
 
 #include <algorithm>
 #include <atomic>
 #include <type_traits>
+#include <vector>
 
 #include "gt_internal.hpp"
 
@@ -44,15 +46,14 @@ struct IgemmArgs {
 
 constexpr int kMfmaWaves = 4, kMT = 4;  // waves per workgroup, 16-pixel M-tiles per wave
 
+// One wave's 64 output pixels m_wave .. m_wave+63 (pixels past a.m_total
+// are skipped) x 16*NT output channels from n_blk.
 template <int R, int S, int C, int NT>
-__global__ __launch_bounds__(256) void igemm_bf16_mfma_kernel(IgemmArgs a) {
+__device__ __forceinline__ void mfma_global_tile(const IgemmArgs &a, int m_wave, int n_blk) {
     constexpr int KC = C / 32;         // 32-channel reduction blocks per (r, s)
     constexpr int STEPS = R * S * KC;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
-    const int m_wave = (blockIdx.x * kMfmaWaves + wave) * (16 * kMT);
-    const int n_blk = blockIdx.y * (16 * NT);
     const unsigned short *in = static_cast<const unsigned short *>(a.in);
     const unsigned short *wt = static_cast<const unsigned short *>(a.w);
 
@@ -136,13 +137,10 @@ __global__ __launch_bounds__(256) void igemm_bf16_mfma_kernel(IgemmArgs a) {
 // (r, s, c-block) walk is a loop with scalar counters instead of a fully
 // unrolled sequence, for filter sizes without a dedicated instance.
 template <int C, int NT>
-__global__ __launch_bounds__(256) void igemm_bf16_mfma_any_kernel(IgemmArgs a, int R, int S) {
+__device__ __forceinline__ void mfma_global_tile_any(const IgemmArgs &a, int R, int S, int m_wave, int n_blk) {
     constexpr int KC = C / 32;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
-    const int m_wave = (blockIdx.x * kMfmaWaves + wave) * (16 * kMT);
-    const int n_blk = blockIdx.y * (16 * NT);
     const unsigned short *in = static_cast<const unsigned short *>(a.in);
     const unsigned short *wt = static_cast<const unsigned short *>(a.w);
 
@@ -230,6 +228,76 @@ __global__ __launch_bounds__(256) void igemm_bf16_mfma_any_kernel(IgemmArgs a, i
                 for (int j = 0; j < NT; ++j) dst[j * 16] = acc[t][j][e];
             }
         }
+}
+
+template <int R, int S, int C, int NT>
+__global__ __launch_bounds__(256) void igemm_bf16_mfma_kernel(IgemmArgs a) {
+    mfma_global_tile<R, S, C, NT>(a, (blockIdx.x * kMfmaWaves + (threadIdx.x >> 6)) * (16 * kMT),
+                                  blockIdx.y * (16 * NT));
+}
+
+template <int C, int NT>
+__global__ __launch_bounds__(256) void igemm_bf16_mfma_any_kernel(IgemmArgs a, int R, int S) {
+    mfma_global_tile_any<C, NT>(a, R, S, (blockIdx.x * kMfmaWaves + (threadIdx.x >> 6)) * (16 * kMT),
+                                blockIdx.y * (16 * NT));
+}
+
+// Many multi-channel convolutions in one persistent launch (the batching
+// form for BF16 requests): one descriptor per convolution (n images of one
+// shape; all share C, c_out, the filter size and the padding), each
+// convolution's pixels cut into blocks of one workgroup (4 waves x 64
+// pixels).  A grid of about the resident capacity strides over the blocks of
+// all convolutions; blockIdx.y picks the output-channel block as in the
+// single launch.  Each block runs the global-load tile above, so a
+// convolution's output is bit for bit that of the global-load kernel.
+struct IgemmBatchDesc {
+    const void *in;
+    const void *w;
+    float *out;
+    int32_t h, wd, out_h, out_w;
+    int32_t ph, pw, m_total, n;
+    int64_t block_begin;  // first block of this convolution in the batch
+};
+static_assert(sizeof(IgemmBatchDesc) == 64, "descriptor layout");
+
+// RS > 0: filter RS x RS unrolled; RS == 0: the runtime size rs
+template <int RS, int C, int NT>
+__global__ __launch_bounds__(256) void igemm_bf16_mfma_batched_kernel(const IgemmBatchDesc *__restrict__ desc,
+                                                                      int n_desc, int64_t total_blocks, int c_out,
+                                                                      int rs) {
+    typedef const __attribute__((address_space(4))) IgemmBatchDesc cdesc;
+    cdesc *d = (cdesc *)desc;
+    for (int64_t item = blockIdx.x; item < total_blocks; item += gridDim.x) {
+        // the convolution holding this block: last descriptor with block_begin <= item
+        int lo = 0, hi = n_desc - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (d[mid].block_begin <= item)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        IgemmArgs a;
+        a.in = d[lo].in;
+        a.w = d[lo].w;
+        a.out = d[lo].out;
+        a.n = d[lo].n;
+        a.h = d[lo].h;
+        a.wd = d[lo].wd;
+        a.c_in = C;
+        a.c_out = c_out;
+        a.out_h = d[lo].out_h;
+        a.out_w = d[lo].out_w;
+        a.ph = d[lo].ph;
+        a.pw = d[lo].pw;
+        a.m_total = d[lo].m_total;
+        const int local = (int)(item - d[lo].block_begin);
+        const int m_wave = (local * kMfmaWaves + (threadIdx.x >> 6)) * (16 * kMT);
+        if constexpr (RS > 0)
+            mfma_global_tile<RS, RS, C, NT>(a, m_wave, blockIdx.y * (16 * NT));
+        else
+            mfma_global_tile_any<C, NT>(a, rs, rs, m_wave, blockIdx.y * (16 * NT));
+    }
 }
 
 // LDS-staged variant.  A workgroup owns a TH-row x 64-column output tile
@@ -887,6 +955,30 @@ const void *mfma_kernel_for(int f, int c, int c_out, bool *generic = nullptr) {
     return fn ? fn : mfma_any_for(c, nt);
 }
 
+// The batched global-load kernel for (filter, c_in, c_out): unrolled for
+// filter sizes 1, 3, 5, 7, the runtime-size walk otherwise.
+#define GT_BM(RS)                                                                           \
+    {RS, 64, 4, (const void *)&igemm_bf16_mfma_batched_kernel<RS, 64, 4>},                 \
+        {RS, 64, 2, (const void *)&igemm_bf16_mfma_batched_kernel<RS, 64, 2>},             \
+        {RS, 32, 4, (const void *)&igemm_bf16_mfma_batched_kernel<RS, 32, 4>},             \
+        {RS, 32, 2, (const void *)&igemm_bf16_mfma_batched_kernel<RS, 32, 2>}
+struct BatchedMfmaEntry {
+    int rs, c, nt;
+    const void *fn;
+};
+const BatchedMfmaEntry kBatchedMfma[] = {GT_BM(0), GT_BM(1), GT_BM(3), GT_BM(5), GT_BM(7)};
+#undef GT_BM
+constexpr size_t kBatchedMfmaSize = sizeof(kBatchedMfma) / sizeof(kBatchedMfma[0]);
+std::atomic<int> g_batched_mfma_occupancy[kBatchedMfmaSize];
+
+const BatchedMfmaEntry *batched_mfma_for(int f, int c, int c_out) {
+    const int nt = (c_out % 64 == 0) ? 4 : 2;
+    const int rs = (f == 1 || f == 3 || f == 5 || f == 7) ? f : 0;
+    for (const BatchedMfmaEntry &e : kBatchedMfma)
+        if (e.rs == rs && e.c == c && e.nt == nt) return &e;
+    return nullptr;
+}
+
 const void *valu_kernel_for(int c) {
     if (c == 64) return (const void *)&igemm_f32_tiled_kernel<64>;
     if (c == 32) return (const void *)&igemm_f32_tiled_kernel<32>;
@@ -1034,4 +1126,104 @@ int launch_igemm(const gt_problem &p, const gt_conv_config &, const void *in, co
     return GT_OK;
 }
 
+
+// Shape checks shared by the batched pack and launch: BF16 MFMA, square
+// filter, channels instantiated.
+static int validate_igemm_batch_shape(const gt_problem &p) {
+    if (p.kind != GT_IGEMM_BF16_MFMA) return set_error(GT_E_UNSUPPORTED, "igemm batch: BF16 MFMA problems only");
+    if (p.filt_h < 1 || p.filt_h != p.filt_w) return set_error(GT_E_UNSUPPORTED, "igemm batch: square filters only");
+    if (p.pad_h < 0 || p.pad_w < 0) return set_error(GT_E_INVAL, "igemm batch: negative padding");
+    if (p.c_out < 32 || p.c_out % 32 != 0)
+        return set_error(GT_E_UNSUPPORTED, "igemm batch: c_out must be a multiple of 32");
+    if (!batched_mfma_for(p.filt_h, p.c_in, p.c_out))
+        return set_error(GT_E_UNSUPPORTED, "igemm batch: c_in %d not instantiated (32 or 64)", p.c_in);
+    return GT_OK;
+}
+
 }  // namespace gt
+
+using namespace gt;
+
+extern "C" int gt_igemm_batch_pack(const gt_problem *shape, const gt_batch_item *items, int32_t n_items,
+                                   void *host_blob, size_t capacity, size_t *blob_bytes, int64_t *total_blocks) {
+    clear_error();
+    if (!shape || !items || n_items < 1 || !blob_bytes || !total_blocks || (capacity && !host_blob))
+        return set_error(GT_E_INVAL, "gt_igemm_batch_pack: bad argument");
+    int rc = validate_igemm_batch_shape(*shape);
+    if (rc) return rc;
+    const int f = shape->filt_h;
+    const size_t need = sizeof(IgemmBatchDesc) * (size_t)n_items;
+    *blob_bytes = need;
+    std::vector<IgemmBatchDesc> d((size_t)n_items);
+    const int64_t per_block = (int64_t)kMfmaWaves * kMT * 16;
+    int64_t blocks = 0;
+    for (int32_t k = 0; k < n_items; ++k) {
+        const gt_batch_item &it = items[k];
+        if (!it.d_in || !it.d_filt || !it.d_out || it.out_h < 1 || it.out_w < 1)
+            return set_error(GT_E_INVAL, "gt_igemm_batch_pack: item %d is not valid", k);
+        if (it.filt_h != f || it.filt_w != f)
+            return set_error(GT_E_INVAL, "gt_igemm_batch_pack: item %d: filter %dx%d, the batch's is %d", k,
+                             it.filt_h, it.filt_w, f);
+        if ((((uintptr_t)it.d_in) | ((uintptr_t)it.d_filt)) & 15)
+            return set_error(GT_E_INVAL, "gt_igemm_batch_pack: item %d: input and weights must be 16-byte aligned", k);
+        const int64_t h = (int64_t)it.out_h + f - 1 - 2 * shape->pad_h, w = (int64_t)it.out_w + f - 1 - 2 * shape->pad_w;
+        if (h < 1 || w < 1) return set_error(GT_E_INVAL, "gt_igemm_batch_pack: item %d: padding too large", k);
+        const int64_t m = (int64_t)it.out_h * it.out_w;
+        if (m >= ((int64_t)1 << 31) - per_block || h * w * shape->c_in >= ((int64_t)1 << 31))
+            return set_error(GT_E_INVAL, "gt_igemm_batch_pack: item %d too large", k);
+        IgemmBatchDesc &x = d[(size_t)k];
+        x.in = it.d_in;
+        x.w = it.d_filt;
+        x.out = static_cast<float *>(it.d_out);
+        x.h = (int32_t)h;
+        x.wd = (int32_t)w;
+        x.out_h = it.out_h;
+        x.out_w = it.out_w;
+        x.ph = shape->pad_h;
+        x.pw = shape->pad_w;
+        x.m_total = (int32_t)m;
+        x.n = 1;
+        x.block_begin = blocks;
+        blocks += (m + per_block - 1) / per_block;
+    }
+    *total_blocks = blocks;
+    if (capacity < need) return set_error(GT_E_CAPACITY, "gt_igemm_batch_pack: %zu bytes needed", need);
+    memcpy(host_blob, d.data(), need);
+    return GT_OK;
+}
+
+extern "C" int conv2d_run_igemm_batched(const gt_problem *shape, const void *d_blob, int32_t n_items,
+                                        int64_t total_blocks, int32_t grid_blocks, void *hip_stream) {
+    clear_error();
+    if (!shape || !d_blob || n_items < 1 || total_blocks < 1)
+        return set_error(GT_E_INVAL, "conv2d_run_igemm_batched: bad argument");
+    if (!state().inited || (state().flags & GT_INIT_HOST_ONLY))
+        return set_error(GT_E_STATE, "conv2d_run_igemm_batched: needs gt_init on a device");
+    if ((uintptr_t)d_blob & 7)
+        return set_error(GT_E_INVAL, "conv2d_run_igemm_batched: descriptor blob must be 8-byte aligned");
+    int rc = validate_igemm_batch_shape(*shape);
+    if (rc) return rc;
+    const BatchedMfmaEntry *e = batched_mfma_for(shape->filt_h, shape->c_in, shape->c_out);
+    const int gy = shape->c_out / (16 * e->nt);
+    int64_t grid;
+    if (grid_blocks <= 0) {
+        // about the resident capacity (surplus blocks are strided over)
+        const size_t idx = (size_t)(e - kBatchedMfma);
+        int occ = g_batched_mfma_occupancy[idx].load(std::memory_order_relaxed);
+        if (occ == 0) {
+            GT_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, e->fn, 256, 0));
+            occ = std::max(1, occ);
+            g_batched_mfma_occupancy[idx].store(occ, std::memory_order_relaxed);
+        }
+        const int64_t resident = std::max<int64_t>(1, (int64_t)std::max(1, state().dev.cu_count) * occ / gy);
+        grid = std::min(total_blocks, resident);
+    } else {
+        grid = std::min<int64_t>(grid_blocks, total_blocks);
+    }
+    const IgemmBatchDesc *desc = static_cast<const IgemmBatchDesc *>(d_blob);
+    int n = n_items, c_out = shape->c_out, rs = shape->filt_h;
+    int64_t tb = total_blocks;
+    void *args[] = {&desc, &n, &tb, &c_out, &rs};
+    GT_HIP_CHECK(hipLaunchKernel(e->fn, dim3((unsigned)grid, (unsigned)gy), dim3(256), args, 0, (hipStream_t)hip_stream));
+    return GT_OK;
+}

@@ -27,9 +27,19 @@ import paper_2211_07260_amd as gt
 from paper_2211_07260_amd import autotune
 
 
+# BF16 requests up to this output side (per filter size) share one
+# persistent launch per step and filter size (batched global-load MFMA
+# kernel, 280-400 TFLOP/s at C = 32); larger ones run the LDS-staged kernel
+# alone, which reuses each input byte across the filter taps but costs a
+# launch of 10-50 us however small the request.  From timing equal-size
+# batches both ways on MI355X: batched ahead up to about these sides.
+BF16_BATCH_SIDE = {3: 384, 5: 256, 9: 160, 17: 160}
+BF16_BATCH_SIDE_OTHER = 160
+
+
 class Request:
     __slots__ = ("rid", "kind", "side", "f", "c", "t_arrive", "seed", "t_admit", "t_done", "bufs", "config",
-                 "bytes")
+                 "bytes", "path")
 
     def __init__(self, rid, kind, side, f, c, t_arrive, seed):
         self.rid, self.kind, self.side, self.f, self.c = rid, kind, side, f, c
@@ -37,6 +47,7 @@ class Request:
         self.t_admit = self.t_done = None
         self.bufs = None
         self.config = None
+        self.path = None  # "batched" (a persistent launch of its step), "single", or "parts"
         self.bytes = footprint(kind, side, f, c)
 
     def flops(self):
@@ -134,15 +145,19 @@ class Engine:
     short work issued meanwhile starts after the running part instead of
     after the whole request (part_flops=None: no parts).  objective: which
     per-size config of the autotuner's store the batched launches use
-    ("time" or "energy")."""
+    ("time" or "energy").  BF16 requests of side at most bf16_batch_side
+    (a {filter: side} dict, or one side for all filters) run as one
+    persistent launch per (filter, channels) of their step (IgemmBatch);
+    larger ones launch alone (0: never batched)."""
 
     def __init__(self, mem_budget=32 << 30, max_slots=512, max_batch=256, n_streams=2, store=None,
                  keep_outputs=False, device="cuda:0", streams=None, long_stream=None, part_flops=1.0e12,
-                 parts_ahead=2, objective="time"):
+                 parts_ahead=2, objective="time", bf16_batch_side=BF16_BATCH_SIDE):
         import torch
         if objective not in autotune.OBJECTIVES:
             raise ValueError("objective must be one of %s" % (autotune.OBJECTIVES,))
         self.objective = objective
+        self.bf16_batch_side = bf16_batch_side
         self.torch = torch
         self.device = torch.device(device)
         self.mem_budget, self.max_slots, self.max_batch = mem_budget, max_slots, max_batch
@@ -161,6 +176,10 @@ class Engine:
         self.slots_used = 0
         self.rejected = []
 
+    def _bf16_side(self, f):
+        b = self.bf16_batch_side
+        return b.get(f, BF16_BATCH_SIDE_OTHER) if isinstance(b, dict) else b
+
     def is_long(self, r):
         return self.part_flops is not None and r.kind == "conv_bf16" and r.flops() > self.part_flops
 
@@ -168,6 +187,7 @@ class Engine:
         with self.torch.cuda.stream(self.long_stream):
             r.bufs = make_payload(r, self.device)
         r.config = (64, 1, 1, 1, 0, 0)
+        r.path = "parts"
         p = gt.conv_problem(gt.IGEMM_BF16_MFMA, 1, r.side, r.side, r.c, r.c, r.f, r.f)
         return LongJob(r, p, max(1, int(math.ceil(r.flops() / self.part_flops))))
 
@@ -210,21 +230,34 @@ class Engine:
             for r in reqs:
                 r.bufs = make_payload(r, self.device)
             groups = collections.defaultdict(list)
+            bf16_groups = collections.defaultdict(list)
             batches = []
             for r in reqs:
                 if r.kind == "xcorr_f32":
                     groups[r.f].append(r)
+                elif r.side <= self._bf16_side(r.f):
+                    bf16_groups[(r.f, r.c)].append(r)
                 else:
                     img, w, out = r.bufs
                     r.config = (64, 1, 1, 1, 0, 0)
+                    r.path = "single"
                     p = gt.conv_problem(gt.IGEMM_BF16_MFMA, 1, r.side, r.side, r.c, r.c, r.f, r.f)
                     gt.conv2d_run(p, r.config, img, w, out, stream=stream)
+            for (f, c), rs in bf16_groups.items():
+                for r in rs:
+                    r.config = (64, 1, 1, 1, 0, 0)
+                    r.path = "batched"
+                b = gt.IgemmBatch([(r.bufs[0][0], r.bufs[1], r.bufs[2][0], r.side, r.side) for r in rs], c, c, f,
+                                  (f - 1) // 2)
+                b.run(stream=stream)
+                batches.append(b)
             for f, rs in groups.items():
                 # config of the group's typical size (work-weighted mean side)
                 side = math.sqrt(sum(r.side ** 2 for r in rs) / len(rs))
                 cfg = autotune.lookup(self.store, f, side, self.objective)
                 for r in rs:
                     r.config = cfg
+                    r.path = "batched"
                 b = gt.Batch([(r.bufs[0], r.bufs[1], r.bufs[2], r.side, r.side, f) for r in rs], cfg)
                 b.run(stream=stream)
                 batches.append(b)
@@ -343,13 +376,14 @@ def energy_stats(samples, t_start, t_stop, n_req, discard_s=0.0):
     return out
 
 
-def benchmark(n_req=8000, seed=0, util=0.7, mem_budget=64 << 30, discard_s=0.3, progress=print):
+def benchmark(n_req=8000, seed=0, util=0.7, mem_budget=64 << 30, discard_s=0.3, progress=print, **engine_kw):
     """The serving-mix benchmark: after one untimed pass that warms the
     device buffer pool, saturation throughput with every request queued at
     t = 0, then Poisson arrivals at util x that rate.  Energy per request is
     the median socket power over that run after a discard_s stabilisation
     prefix, times the run's length, over the requests served (section III.A-B:
-    the run should last well over a second).  Returns a report dict (latency
+    the run should last well over a second).  engine_kw go to every Engine
+    (e.g. objective, bf16_batch_side).  Returns a report dict (latency
     percentiles, throughput, energy per request)."""
     import torch
     from synthetic import serving_requests
@@ -359,10 +393,10 @@ def benchmark(n_req=8000, seed=0, util=0.7, mem_budget=64 << 30, discard_s=0.3, 
     # device buffers, and first-time device allocation is not request work
     streams = [torch.cuda.Stream() for _ in range(2)]
     long_stream = torch.cuda.Stream()
-    Engine(mem_budget=mem_budget, streams=streams, long_stream=long_stream).run(requests_from_mix(mix),
+    Engine(mem_budget=mem_budget, streams=streams, long_stream=long_stream, **engine_kw).run(requests_from_mix(mix),
                                                                               realtime=False)
     # saturation
-    eng = Engine(mem_budget=mem_budget, streams=streams, long_stream=long_stream)
+    eng = Engine(mem_budget=mem_budget, streams=streams, long_stream=long_stream, **engine_kw)
     reqs = requests_from_mix(mix)
     t0 = time.perf_counter()
     done = eng.run(reqs, realtime=False)
@@ -373,7 +407,7 @@ def benchmark(n_req=8000, seed=0, util=0.7, mem_budget=64 << 30, discard_s=0.3, 
     progress("saturation: %d requests in %.3f s (%.1f req/s)" % (len(done), t_sat, mu))
     lam = util * mu
     reqs = requests_from_mix(mix, rate_scale=1.0 / lam)
-    eng = Engine(mem_budget=mem_budget, streams=streams, long_stream=long_stream)
+    eng = Engine(mem_budget=mem_budget, streams=streams, long_stream=long_stream, **engine_kw)
     gt.sampler_start(2.0)
     t_start = gt.sensor_read()["t_s"]
     t0 = time.perf_counter()

@@ -350,3 +350,42 @@ def test_fit_covariance_measured_voltage_and_undefined():
     r4 = gt.fit_power_model(f[:4], p[:4] * 0 + _synth(f[:4], dict(p_idle=150, alpha=0.2, beta=1e-3, tau=1100,
                                                                    p_max=1e9)), 1e9)
     assert np.all(np.isnan(np.array(r4.covariance())))
+
+
+def test_igemm_batch_pack_host():
+    # descriptors of the batched multi-channel launch: one per convolution,
+    # blocks of 256 output pixels, first-block indices in order
+    import ctypes
+    lib = gt.lib()
+    shape = gt.conv_problem(gt.IGEMM_BF16_MFMA, 1, 1, 1, 32, 32, 5, 5)
+    sides = [(1, 1), (16, 16), (17, 15), (100, 3), (257, 1)]
+    items = (gt.BatchItem * len(sides))()
+    for k, (oh, ow) in enumerate(sides):
+        items[k] = gt.BatchItem(0x10000 * (k + 1), 0x20000000 + 0x100 * k, 0x30000000, oh, ow, 5, 5)
+    nb, tb = ctypes.c_size_t(0), ctypes.c_int64(0)
+    assert lib.gt_igemm_batch_pack(ctypes.byref(shape), items, len(sides), None, 0, ctypes.byref(nb),
+                                   ctypes.byref(tb)) == gt.GT_E_CAPACITY
+    blocks = [-(-oh * ow // 256) for oh, ow in sides]
+    assert nb.value == 64 * len(sides) and tb.value == sum(blocks)
+    blob = (ctypes.c_uint8 * nb.value)()
+    assert lib.gt_igemm_batch_pack(ctypes.byref(shape), items, len(sides), blob, nb.value, ctypes.byref(nb),
+                                   ctypes.byref(tb)) == gt.GT_OK
+    raw = bytes(blob)
+    begin = 0
+    for k, (oh, ow) in enumerate(sides):
+        rec = raw[64 * k:64 * (k + 1)]
+        h, wd, o_h, o_w, ph, pw, m, n = np.frombuffer(rec[24:56], dtype=np.int32)
+        assert (h, wd, o_h, o_w, ph, pw, m, n) == (oh, ow, oh, ow, 2, 2, oh * ow, 1)  # same padding
+        assert np.frombuffer(rec[56:64], dtype=np.int64)[0] == begin
+        begin += blocks[k]
+    # rejections: unaligned input, filter mismatch, channels not instantiated, BF16 only
+    bad = (gt.BatchItem * 1)(gt.BatchItem(0x10008, 0x20000, 0x30000, 4, 4, 5, 5))
+    assert lib.gt_igemm_batch_pack(ctypes.byref(shape), bad, 1, None, 0, ctypes.byref(nb),
+                                   ctypes.byref(tb)) == gt.GT_E_INVAL
+    bad = (gt.BatchItem * 1)(gt.BatchItem(0x10000, 0x20000, 0x30000, 4, 4, 3, 3))
+    assert lib.gt_igemm_batch_pack(ctypes.byref(shape), bad, 1, None, 0, ctypes.byref(nb),
+                                   ctypes.byref(tb)) == gt.GT_E_INVAL
+    for sh in (gt.conv_problem(gt.IGEMM_BF16_MFMA, 1, 1, 1, 48, 32, 5, 5),
+               gt.conv_problem(gt.IGEMM_F32_VALU, 1, 1, 1, 32, 64, 5, 5)):
+        assert lib.gt_igemm_batch_pack(ctypes.byref(sh), items, len(sides), None, 0, ctypes.byref(nb),
+                                       ctypes.byref(tb)) == gt.GT_E_UNSUPPORTED

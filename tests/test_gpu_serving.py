@@ -60,13 +60,19 @@ def test_alone_equals_mix(gt, part_flops):
     done = eng.run(reqs, realtime=True)
     assert len(done) == len(reqs)
     dev = torch.device("cuda:0")
+    paths = {r.path for r in done if r.kind == "conv_bf16"}
+    # sides 16-160: every BF16 request is batched, unless it runs in parts
+    assert paths == {"batched"} if part_flops is None else "parts" in paths
     for r in done:
         img, w, out = serving.make_payload(r, dev)
         if r.kind == "xcorr_f32":
             p = gt.xcorr_problem(r.side, r.side, r.f, r.f)
+            gt.conv2d_run(p, r.config, img, w, out)
+        elif r.path == "batched":  # alone: a batch of one, the same kernel
+            gt.IgemmBatch([(img[0], w, out[0], r.side, r.side)], r.c, r.c, r.f, (r.f - 1) // 2).run()
         else:
             p = gt.conv_problem(gt.IGEMM_BF16_MFMA, 1, r.side, r.side, r.c, r.c, r.f, r.f)
-        gt.conv2d_run(p, r.config, img, w, out)
+            gt.conv2d_run(p, r.config, img, w, out)
         torch.cuda.synchronize()
         assert torch.equal(out, eng.outputs[r.rid]), (r.rid, r.kind, r.side, r.f)
         # every request of the mix against the oracle
