@@ -12,7 +12,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgreentune.so")
+# GREENTUNE_LIB selects another build of the same library (the host-sanitizer
+# build of the tests); by default the one built in this package directory
+LIB_PATH = os.environ.get("GREENTUNE_LIB") or os.path.join(_HERE, "libgreentune.so")
 
 # ---- constants mirrored from include/greentune.h ----
 GT_OK, GT_E_INVAL, GT_E_UNSUPPORTED, GT_E_PERM = 0, -1, -2, -3
@@ -482,7 +484,29 @@ def set_dvfs_backend(apply, restore=None):
     if not _backend_refs:
         import atexit
         atexit.register(_lib.gt_shutdown)  # restore the knob on a normal exit
+        _restore_on_sigterm()
     _backend_refs[:] = [a, r, b]
+
+
+def _restore_on_sigterm():
+    """A terminated tuner restores the DVFS knob too: SIGTERM (the default
+    action ends the process without running atexit) first calls
+    gt_shutdown, then the handler that was installed before, or the default
+    action.  Only from the main thread, where Python allows handlers."""
+    import signal
+    import threading
+    if threading.current_thread() is not threading.main_thread():
+        return
+    prev = signal.getsignal(signal.SIGTERM)
+
+    def handler(signum, frame):
+        _lib.gt_shutdown()
+        if callable(prev):
+            prev(signum, frame)
+        else:
+            signal.signal(signum, signal.SIG_DFL)
+            os.kill(os.getpid(), signum)
+    signal.signal(signal.SIGTERM, handler)
 
 
 def dvfs_state():

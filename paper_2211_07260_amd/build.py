@@ -2,7 +2,8 @@
 
 Every source under csrc/ (HIP kernels and host C++) is compiled to an object
 under <repo>/_build/ in parallel, then linked with amd-smi.  All device code
-is compiled with packed FP32 instructions disabled.
+is compiled with packed FP32 instructions disabled.  The measurement window is
+marked with a roctx range (rocprofiler-sdk-roctx).
 """
 import concurrent.futures as cf
 import glob
@@ -57,7 +58,7 @@ def build(jobs=None, verbose=False):
     # HIP comes from torch's runtime, amd-smi from ROCm.
     cmd = ["g++", "-shared", "-fPIC", "-o", tmp] + objs + [
         "-L" + tlib, "-l:libamdhip64.so", "-Wl,-rpath," + tlib,
-        "-L" + os.path.join(ROCM, "lib"), "-lamd_smi", "-Wl,-rpath," + os.path.join(ROCM, "lib"),
+        "-L" + os.path.join(ROCM, "lib"), "-lamd_smi", "-lrocprofiler-sdk-roctx", "-Wl,-rpath," + os.path.join(ROCM, "lib"),
         "-Wl,--no-undefined", "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -10,8 +10,11 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdio>
 #include <functional>
 #include <thread>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "gt_internal.hpp"
 
@@ -63,6 +66,15 @@ void record_last_window(const std::vector<gt_sensor_sample> &samples, double t_s
 }  // namespace
 
 namespace gt {
+
+// Marker text of a measurement window: its work per launch (flop, or bytes
+// for the copy load) and options.
+static std::string gflops_label(double flops, const gt_measure_opts &o) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "greentune measure window: %.4g G work/launch, %.3g s, discard %.3g s%s", flops * 1e-9,
+             o.window_s, o.discard_s, o.use_graph ? ", graph replay" : "");
+    return buf;
+}
 
 // A kept window at least this long whose power never changes is stale: the
 // socket power reading refreshes every few milliseconds under load.
@@ -152,6 +164,9 @@ int measure_window(const std::function<int(hipStream_t)> &launch, double flops_p
             std::this_thread::sleep_for(period);
         }
     });
+    // a marker range around the window (rocprofv3 --marker-trace shows it
+    // beside the kernels it times); no-op without a profiler
+    roctxRangePushA(gflops_label(flops_per_launch, o).c_str());
     const double t_start = now_s();
     hipError_t herr = hipEventRecord(win.a, s);
     int64_t launched = 0;
@@ -162,6 +177,7 @@ int measure_window(const std::function<int(hipStream_t)> &launch, double flops_p
     if (herr == hipSuccess && rc == GT_OK) herr = hipEventRecord(win.b, s);
     if (herr == hipSuccess && rc == GT_OK) herr = hipEventSynchronize(win.b);
     const double t_stop = now_s();
+    roctxRangePop();
     stop.store(true);
     sampler.join();
     sensor_set_busy(false);

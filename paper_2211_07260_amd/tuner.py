@@ -84,13 +84,17 @@ def sweep(problem, configs, d_in, d_w, d_out, clk=None, window_s=0.3, discard_s=
     skipped.  time_only: time with HIP events only (no sensor), for the
     performance landscape."""
     import torch
+    clk_name = "default" if clk is None or clk.kind == gt.CLOCK_DEFAULT else "%d:%d" % (clk.kind, clk.value)
+    # a logged row is reused only for the same device, problem and options
+    ctx = "%s|%s|%s|%s" % (device_id(), ",".join(str(v) for v in problem_tuple(problem)),
+                           "time_only" if time_only else "%g,%g" % (window_s, discard_s), clk_name)
     done = {}
     if log_path and resume and os.path.exists(log_path):
         with open(log_path) as fh:
             for ln in fh:
                 r = json.loads(ln)
-                done[(r["config_key"], r.get("clock", "default"))] = r
-    clk_name = "default" if clk is None or clk.kind == gt.CLOCK_DEFAULT else "%d:%d" % (clk.kind, clk.value)
+                if r.get("context", ctx) == ctx:
+                    done[(r["config_key"], r.get("clock", "default"))] = r
     rows = []
     fh = open(log_path, "a") if log_path else None
     t0 = time.perf_counter()
@@ -100,7 +104,7 @@ def sweep(problem, configs, d_in, d_w, d_out, clk=None, window_s=0.3, discard_s=
             if (key, clk_name) in done:
                 rows.append(done[(key, clk_name)])
                 continue
-            row = {"config": list(gt.as_config(cfg).as_tuple()), "config_key": key, "clock": clk_name}
+            row = {"config": list(gt.as_config(cfg).as_tuple()), "config_key": key, "clock": clk_name, "context": ctx}
             try:
                 if time_only:
                     for _ in range(2):
@@ -134,6 +138,24 @@ def sweep(problem, configs, d_in, d_w, d_out, clk=None, window_s=0.3, discard_s=
         if fh:
             fh.close()
     return rows
+
+
+def device_id():
+    """Identity of GPU 0 for result logs: its UUID where torch reports one,
+    else its name and PCI bus id ("cpu" without a GPU)."""
+    import torch
+    if not torch.cuda.is_available():
+        return "cpu"
+    props = torch.cuda.get_device_properties(0)
+    uuid = getattr(props, "uuid", None)
+    if uuid:
+        return str(uuid)
+    return "%s@%s" % (props.name, getattr(props, "pci_bus_id", "?"))
+
+
+def problem_tuple(problem):
+    return (problem.kind, problem.n, problem.c_in, problem.c_out, problem.out_h, problem.out_w, problem.filt_h,
+            problem.filt_w, problem.pad_h, problem.pad_w)
 
 
 def optima(rows):
