@@ -173,18 +173,39 @@ def time_bucket(f, side, reps=50, store=None, objective="time"):
             "tflops": flops / t / 1e12}
 
 
+def time_bf16_batch(f, side, c=32, reps=50):
+    """Time one batched BF16 multi-channel launch (IgemmBatch) over a batch
+    of equal-size requests of about 1 M output pixels in total (N = 1 each,
+    c input and output channels, same padding), as one persistent launch per
+    repetition.  Returns a dict with the batch size, ms per launch and
+    TFLOP/s."""
+    import torch
+    dev = torch.device("cuda:0")
+    n = max(1, (1024 * 1024) // (side * side))
+    x = torch.randn(n, side, side, c, device=dev).to(torch.bfloat16)
+    w = torch.randn(n, c, f, f, c, device=dev).to(torch.bfloat16)
+    o = torch.empty(n, side, side, c, device=dev)
+    b = gt.IgemmBatch([(x[k], w[k], o[k], side, side) for k in range(n)], c, c, f, (f - 1) // 2)
+    t = time_batch(b, reps)
+    return {"filter": f, "side": side, "c": c, "batch": n, "ms": t * 1e3, "tflops": b.flops() / t / 1e12}
+
+
 if __name__ == "__main__":
     import argparse
     ap = argparse.ArgumentParser(description="per-size autotuner for the batched launch")
     ap.add_argument("--time", nargs=2, type=int, metavar=("FILTER", "SIDE"),
                     help="time the stored config of one bucket instead of tuning")
+    ap.add_argument("--bf16-time", nargs=2, type=int, metavar=("FILTER", "SIDE"),
+                    help="time a batched BF16 multi-channel launch (C=32) of equal-size requests instead")
     ap.add_argument("--objective", choices=OBJECTIVES, default="time")
     ap.add_argument("--reps", type=int, default=50)
     ap.add_argument("--filters", type=str, default=None, help="comma-separated subset of the filter sizes")
     ap.add_argument("--out", type=str, default=STORE)
     args = ap.parse_args()
     gt.init(0, 0)
-    if args.time:
+    if args.bf16_time:
+        print(json.dumps(time_bf16_batch(args.bf16_time[0], args.bf16_time[1], reps=args.reps)), flush=True)
+    elif args.time:
         print(json.dumps(time_bucket(args.time[0], args.time[1], args.reps, objective=args.objective)), flush=True)
     else:
         filters = tuple(int(v) for v in args.filters.split(",")) if args.filters else FILTERS
