@@ -282,8 +282,16 @@ def main():
                                     "in_force": None if cur != cur else cur}
         except gt.GreentuneError as e:
             loads["power_cap_w"] = {"error": str(e)}
+        # the clock knob's range as the device reports it (read only): the
+        # clock points an exhaustive sweep of one config would measure
+        try:
+            clocks = gt.settable_clocks(25.0)
+            loads["gfx_clock_mhz"] = {"min": clocks[0], "max": clocks[-1], "points_at_25_mhz": len(clocks),
+                                      "knob_changes_permitted": False}
+        except gt.GreentuneError as e:
+            loads["gfx_clock_mhz"] = {"error": str(e)}
         print("bench: synthetic loads " + ", ".join("%s %.0f W" % (k, v.get("p_median_w", float("nan")))
-                                                     for k, v in loads.items() if k != "power_cap_w"),
+                                                     for k, v in loads.items() if k not in ("power_cap_w", "gfx_clock_mhz")),
               file=sys.stderr, flush=True)
 
     extras = None
