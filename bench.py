@@ -12,6 +12,7 @@ JSON line.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -21,6 +22,7 @@ sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3    # MI355X published FP32 vector peak (packed FMA, 2.4 GHz)
 FP32_NONPACKED_PEAK_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 flop x 2.4 GHz (one FMA per lane per clock)
+PEAK_CLOCK_MHZ = 2400.0  # the graphics clock both peaks are quoted at
 TUNED = os.path.join(ROOT, "paper_2211_07260_amd", "tuned", "xcorr_f32_4096x4096_f17.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "xcorr_f32_4096x4096_f17_traffic.json")
 DEFAULT_CFG = (32, 8, 4, 4, 0, 0)
@@ -343,6 +345,16 @@ def main():
                      "frac_of_nonpacked_peak": round(achieved / FP32_NONPACKED_PEAK_TFLOPS, 4),
                      "traffic": traffic},
     }
+    # the peak scaled to the clock the device actually ran: the mean graphics
+    # clock over the energy window of the same config (same load, right after
+    # the timed region); absent when no fresh clock reading came in that window
+    sclk = (energy or {}).get("time_tuned", {}).get("sclk_act_mhz")
+    if sclk is not None and math.isfinite(sclk) and sclk > 0:
+        scale = sclk / PEAK_CLOCK_MHZ
+        result["roofline"].update(
+            clock_mhz_measured=round(sclk, 1),
+            frac_at_measured_clock=round(achieved / (FP32_VECTOR_PEAK_TFLOPS * scale), 4),
+            frac_of_nonpacked_peak_at_measured_clock=round(achieved / (FP32_NONPACKED_PEAK_TFLOPS * scale), 4))
     result.update(synthetic_loads=loads, multichannel=extras, serving=serving_rep)
     gain = (energy or {}).get("efficiency_gain_energy_vs_time")
     result["targets"] = {
