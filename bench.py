@@ -23,6 +23,8 @@ sys.path.insert(0, ROOT)
 FP32_VECTOR_PEAK_TFLOPS = 157.3    # MI355X published FP32 vector peak (packed FMA, 2.4 GHz)
 FP32_NONPACKED_PEAK_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 flop x 2.4 GHz (one FMA per lane per clock)
 PEAK_CLOCK_MHZ = 2400.0  # the graphics clock both peaks are quoted at
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E bandwidth
 TUNED = os.path.join(ROOT, "paper_2211_07260_amd", "tuned", "xcorr_f32_4096x4096_f17.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "xcorr_f32_4096x4096_f17_traffic.json")
 DEFAULT_CFG = (32, 8, 4, 4, 0, 0)
@@ -141,7 +143,8 @@ def igemm_extras(gt, torch, dev, steps=200, energy=True, outputs=None, warmup_s=
             e1.record()
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / steps
-            r = {"ms": round(ms, 5), "tflops": round(gt.problem_flops(p) / ms / 1e9, 2)}
+            r = {"ms": round(ms, 5), "tflops": round(gt.problem_flops(p) / ms / 1e9, 2),
+                 "roofline": multichannel_roofline(kind == gt.IGEMM_BF16_MFMA, f, gt.problem_flops(p), ms)}
             if energy:
                 try:
                     m = gt.measure_time_energy(p, (64, 1, 1, 1, 0, 0), dx, dw, out, window_s=1.0, discard_s=0.3)
@@ -154,6 +157,34 @@ def igemm_extras(gt, torch, dev, steps=200, energy=True, outputs=None, warmup_s=
                 torch.cuda.synchronize()
                 outputs["%s_f%d" % (name, f)] = out.cpu().numpy()
     return res
+
+
+def multichannel_roofline(bf16, f, flops, ms, n=16, side=128, c=64):
+    """Roofline entry of one multi-channel run: algorithmic bytes are the
+    input and weights once (BF16 or FP32) and the FP32 output once; the bound
+    is HBM when flop/byte is below the ridge of the path's peak (BF16 dense
+    MFMA 2.5 PFLOP/s, FP32 vector 157.3 TFLOP/s, over 8 TB/s), else compute."""
+    eb = 2 if bf16 else 4
+    nbytes = n * side * side * c * eb + c * f * f * c * eb + n * side * side * c * 4
+    peak = BF16_MFMA_PEAK_TFLOPS if bf16 else FP32_VECTOR_PEAK_TFLOPS
+    if flops / nbytes < peak * 1e12 / (HBM_PEAK_GBS * 1e9):
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": nbytes}
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"bound": "mfma" if bf16 else "alu", "achieved": round(tf, 2), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(tf / peak, 4), "algorithmic_bytes": nbytes}
+
+
+def finite_or_none(v):
+    """The result with every non-finite float replaced by null (strict JSON)."""
+    if isinstance(v, float):
+        return v if math.isfinite(v) else None
+    if isinstance(v, dict):
+        return {k: finite_or_none(x) for k, x in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [finite_or_none(x) for x in v]
+    return v
 
 
 def synthetic_loads(gt, torch, dev):
@@ -389,7 +420,7 @@ def main():
             if extras and name in extras:
                 extras[name]["max_rel_err_vs_oracle"] = e
     gt.shutdown()
-    print(json.dumps(result), flush=True)
+    print(json.dumps(finite_or_none(result), allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":
