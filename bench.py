@@ -147,7 +147,8 @@ def igemm_extras(gt, torch, dev, steps=200, energy=True, outputs=None, warmup_s=
                  "roofline": multichannel_roofline(kind == gt.IGEMM_BF16_MFMA, f, gt.problem_flops(p), ms)}
             if energy:
                 try:
-                    m = gt.measure_time_energy(p, (64, 1, 1, 1, 0, 0), dx, dw, out, window_s=1.0, discard_s=0.3)
+                    # 1.3 s kept: at least one refresh of the once-a-second clock reading
+                    m = gt.measure_time_energy(p, (64, 1, 1, 1, 0, 0), dx, dw, out, window_s=1.6, discard_s=0.3)
                     r.update(gflops_per_w=round(m["gflops_per_w"], 3), p_median_w=m["p_median_w"],
                              sclk_mhz=round(m["sclk_act_mhz"], 1))
                 except gt.GreentuneError as e:
