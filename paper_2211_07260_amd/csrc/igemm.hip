@@ -431,9 +431,11 @@ struct HaloRows {
 // registers while the tile computes and written to LDS once every wave is
 // done with the rows they replace.
 // TH output rows (= waves) per workgroup; WM: weight placement (WeightMode).
-template <int C, int NT, int R, int S, int TH, int WM>
-__global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, int tiles_per_wg, int tile_lo,
-                                                                 int tile_hi) {
+// G: channel groups per workgroup (G * TH waves; wave w computes output row
+// w % TH for the group's 16*NT channels w / TH, all groups sharing the halo).
+template <int C, int NT, int R, int S, int TH, int WM, int G = 1>
+__global__ __launch_bounds__(TH * G * 64) void igemm_bf16_lds_kernel(IgemmArgs a, int tiles_per_wg, int tile_lo,
+                                                                     int tile_hi) {
     constexpr int WP = WM & 3;  // weight placement
     constexpr bool WL = WP == kWeightsLds, WSLAB = WP == kWeightsLdsBySlab || WP == kWeightsLdsByRow;
     constexpr bool STREAM = (WM & kHaloStream) != 0;
@@ -445,7 +447,8 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
     // Otherwise the whole halo is kept as a ring shared with the next tile
     // down the strip.
     constexpr int NSLOT = STREAM ? TH + 1 : HH;
-    constexpr int NTHR = TH * 64;
+    constexpr int NTHR = TH * G * 64;
+    constexpr int NTG = NT * G;  // 16-channel N-tiles of the workgroup
     typedef HaloRows<C, HW, NSLOT, NTHR, HH> Full;
     typedef HaloRows<C, HW, NSLOT, NTHR, TH> Next;
     typedef HaloRows<C, HW, NSLOT, NTHR, 1> One;
@@ -455,10 +458,10 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
     constexpr int ENDR = TH - PROG;
     typedef HaloRows<C, HW, NSLOT, NTHR, (ENDR > 0 ? ENDR : 1)> EndRows;
     constexpr int HW4 = Full::HW4, ROWB = Full::ROWB, PLANE = Full::PLANE;
-    constexpr int TAPB = 16 * NT * kRec;  // one (tap, c-block) of the workgroup's weights
-    constexpr int SLAB_BYTES = S * NKC * TAPB;    // one slab of weights
-    constexpr int WCHUNK = 16 * NT * R * S * CH;  // this workgroup's weight chunks
-    constexpr int SCHUNK = 16 * NT * S * NKC * 4; // ... of one slab
+    constexpr int TAPB = 16 * NTG * kRec;  // one (tap, c-block) of the workgroup's weights
+    constexpr int SLAB_BYTES = S * NKC * TAPB;     // one slab of weights
+    constexpr int WCHUNK = 16 * NTG * R * S * CH;  // this workgroup's weight chunks
+    constexpr int SCHUNK = 16 * NTG * S * NKC * 4; // ... of one slab
     // Ring modes: the next tile's TH new halo rows replace rows this tile has
     // finished with; with all weights in LDS they are prefetched into
     // registers while the tile computes and stored after it; with weights
@@ -473,6 +476,7 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
     unsigned char *wlds = lds;
     unsigned char *halo = lds + (WL ? R * S * KC * TAPB : WSLAB ? 2 * SLAB_BYTES : 0);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = wave % TH, n_w = (wave / TH) * (16 * NT);  // this wave's output row and channel offset
     const int li = lane & 15, lg = lane >> 4;
     const int tiles_x = (a.out_w + kLdsTW - 1) / kLdsTW, tiles_y = (a.out_h + TH - 1) / TH;
     // This launch covers tiles [tile_lo, tile_hi) of the a.n * tiles_x *
@@ -485,7 +489,7 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
     const int t_begin = tile_lo + g * tiles_per_wg;
     const int t_end = min(tile_hi, t_begin + tiles_per_wg);
     if (t_begin >= t_end) return;  // uniform over the workgroup
-    const int n_blk = blockIdx.y * (16 * NT);
+    const int n_blk = blockIdx.y * (16 * NTG);
     const unsigned short *wt = static_cast<const unsigned short *>(a.w);
 
     // tile t -> (image b, column strip, row block), row block fastest
@@ -499,7 +503,7 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
     };
     // weight chunk q of (channel cl, tap) -> LDS offset within a [tap][c-block][channel] block
     auto wofs = [&](int tap, int cl, int q) {
-        return ((tap * KC + (q >> 2)) * (16 * NT) + cl) * kRec + 16 * rec_slot(q & 3, cl);
+        return ((tap * KC + (q >> 2)) * (16 * NTG) + cl) * kRec + 16 * rec_slot(q & 3, cl);
     };
     // one slab of weights (slab modes): slab z = filter row r = z * NKC / KC,
     // c-blocks kc0 = z * NKC % KC .. kc0 + NKC - 1; chunk k = (channel cl,
@@ -524,7 +528,7 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
             const int cl = k / (S * NKC * 4), rem = k - cl * (S * NKC * 4);
             const int sx = rem / (NKC * 4), c = rem - sx * (NKC * 4);
             if (k < SCHUNK)
-                *reinterpret_cast<u32x4 *>(wlds + buf * SLAB_BYTES + ((sx * NKC + (c >> 2)) * (16 * NT) + cl) * kRec +
+                *reinterpret_cast<u32x4 *>(wlds + buf * SLAB_BYTES + ((sx * NKC + (c >> 2)) * (16 * NTG) + cl) * kRec +
                                            16 * rec_slot(c & 3, cl)) = v[it];
         }
     };
@@ -545,7 +549,7 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
         }
     }
     if constexpr (WL) {
-        // all weights of output channels n_blk .. n_blk + 16*NT, staged once:
+        // all weights of output channels n_blk .. n_blk + 16*NTG, staged once:
         // chunk k = (channel cl, tap rs, chunk q)
         constexpr int ITERS = (WCHUNK + NTHR - 1) / NTHR;
         u32x4 v[ITERS];
@@ -589,7 +593,8 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
     constexpr int NS = NKC * S;          // steps per pass
     constexpr bool UNROLLED = WSLAB || R <= 7;
     // Deferred output stores: with the passes unrolled, the weights in LDS
-    // and one wave per SIMD (registers to spare), a tile's results stay in
+    // and four-row tiles (one wave per SIMD, or two with two channel groups
+    // of 32 channels: registers to spare either way), a tile's results stay in
     // registers and are stored during the next tile's first passes, instead
     // of every workgroup storing at once at its tile end while the matrix
     // cores idle.  (With weights read from L2, each weight load would wait
@@ -674,19 +679,19 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
         // fragments BD steps ahead.  mid() runs halfway.
         auto pass = [&](int z, auto &&mid) {
             const int r = z * NKC / KC, kc0 = z * NKC - r * KC;
-            const unsigned char *arow = halo + ((STREAM ? wave + r : y0 + wave + r) % NSLOT) * ROWB;
+            const unsigned char *arow = halo + ((STREAM ? row + r : y0 + row + r) % NSLOT) * ROWB;
             u32x4 Af[NKC][kMT + S - 1], Bq[NS][NT];
             auto ld_b = [&](int k) {
                 const int kk = k / S, s = k - kk * S, kc = kc0 + kk;
 #pragma unroll
                 for (int j = 0; j < NT; ++j) {
                     if constexpr (WL) {
-                        Bq[k][j] = *reinterpret_cast<const u32x4 *>(wlds + ((r * S + s) * KC + kc) * TAPB + j * 16 * kRec + bofs);
+                        Bq[k][j] = *reinterpret_cast<const u32x4 *>(wlds + ((r * S + s) * KC + kc) * TAPB + n_w * kRec + j * 16 * kRec + bofs);
                     } else if constexpr (WSLAB) {
-                        Bq[k][j] = *reinterpret_cast<const u32x4 *>(wlds + wb * SLAB_BYTES + (s * NKC + kk) * TAPB + j * 16 * kRec + bofs);
+                        Bq[k][j] = *reinterpret_cast<const u32x4 *>(wlds + wb * SLAB_BYTES + (s * NKC + kk) * TAPB + n_w * kRec + j * 16 * kRec + bofs);
                     } else {
                         Bq[k][j] = *reinterpret_cast<const u32x4 *>(
-                            wtt + (((size_t)(n_blk + j * 16 + li) * R + r) * S + s) * C + kc * 32 + lg * 8);
+                            wtt + (((size_t)(n_blk + n_w + j * 16 + li) * R + r) * S + s) * C + kc * 32 + lg * 8);
                     }
                 }
             };
@@ -790,10 +795,10 @@ __global__ __launch_bounds__(TH * 64) void igemm_bf16_lds_kernel(IgemmArgs a, in
         // 16*j + 4*lg + e of pixel x0 + 4*li + m; stored in pairs (see
         // store_q): the even lane of a pair writes channels 16*j + 4*lg of
         // both pixels, the odd lane channels 16*(j+1) + 4*lg
-        const int y = y0 + wave;
+        const int y = y0 + row;
         pending = y < a.out_h;
         const int xe = x0 + 4 * (li & ~1);
-        sv_dst = a.out + (((size_t)b * a.out_h + y) * a.out_w + xe) * a.c_out + n_blk + 16 * (li & 1) + 4 * lg;
+        sv_dst = a.out + (((size_t)b * a.out_h + y) * a.out_w + xe) * a.c_out + n_blk + n_w + 16 * (li & 1) + 4 * lg;
         sv_xl0 = min(kMT, a.out_w - xe);
         sv_xl1 = min(kMT, a.out_w - (xe + 4));
 #pragma unroll
@@ -986,35 +991,47 @@ const void *valu_kernel_for(int c) {
 }
 
 struct LdsEntry {
-    int c, nt, f;
+    int c, nt, f;  // nt: 16-channel N-tiles per workgroup
     const void *fn;
     int lds, th, threads;
+    int g;  // channel groups per workgroup
 };
 #define GT_L(C, NT, F)                                                                                     \
     {C, NT, F, (const void *)&igemm_bf16_lds_kernel<C, NT, F, F, LdsPlan<C, NT, F>::TH, LdsPlan<C, NT, F>::WM>, \
-     LdsPlan<C, NT, F>::bytes, LdsPlan<C, NT, F>::TH, LdsPlan<C, NT, F>::threads}
+     LdsPlan<C, NT, F>::bytes, LdsPlan<C, NT, F>::TH, LdsPlan<C, NT, F>::threads, 1}
+// two channel groups of NT N-tiles, all weights in LDS, the halo a ring of TH+F-1 rows
+#define GT_LG(C, NT, F, TH)                                                                                  \
+    {C, 2 * NT, F, (const void *)&igemm_bf16_lds_kernel<C, NT, F, F, TH, kWeightsLds, 2>,                     \
+     LdsPlan<C, 2 * NT, F>::ring(TH) + LdsPlan<C, 2 * NT, F>::wbytes, TH, 2 * TH * 64, 2}
 const LdsEntry kLdsTable[] = {
     GT_L(64, 4, 1), GT_L(64, 4, 3), GT_L(64, 4, 5), GT_L(64, 4, 7), GT_L(64, 4, 9),
     GT_L(64, 2, 1), GT_L(64, 2, 3), GT_L(64, 2, 5), GT_L(64, 2, 7), GT_L(64, 2, 9),
     GT_L(32, 4, 1), GT_L(32, 4, 3), GT_L(32, 4, 5), GT_L(32, 4, 7), GT_L(32, 4, 9), GT_L(32, 4, 17),
     GT_L(32, 2, 1), GT_L(32, 2, 3), GT_L(32, 2, 5), GT_L(32, 2, 7), GT_L(32, 2, 9), GT_L(32, 2, 17),
+    GT_LG(64, 2, 3, 4), GT_LG(32, 2, 3, 4),
 };
 #undef GT_L
+#undef GT_LG
 constexpr size_t kLdsTableSize = sizeof(kLdsTable) / sizeof(kLdsTable[0]);
 std::atomic<int> g_lds_occupancy[kLdsTableSize];  // resident workgroups per CU, 0 = not yet queried
 
-const LdsEntry *lds_entry(int f, int c, int nt) {
+const LdsEntry *lds_entry(int f, int c, int nt, int g = 1) {
     for (const LdsEntry &e : kLdsTable)
-        if (e.c == c && e.nt == nt && e.f == f && e.lds <= state().dev.lds_per_block) return &e;
+        if (e.g == g && e.c == c && e.nt == nt && e.f == f && e.lds <= state().dev.lds_per_block) return &e;
     return nullptr;
 }
 
 // The LDS-staged kernel for (c_in, c_out, f) when instantiated and its LDS
-// fits the device; null otherwise.  With c_out a multiple of 64, workgroups
-// of 64 output channels, unless only 32-channel workgroups get eight rows
-// (two waves per SIMD); measured on 5x5, C=64: 0.059 -> 0.055 ms.
+// fits the device; null otherwise.  With c_out a multiple of 64: the
+// two-group kernel where there is one (3x3: four-row tiles of 64 channels,
+// two waves per SIMD, four tiles per workgroup at N=16, 128x128 instead of
+// two, so loads and stores overlap more of the compute; 0-10 % faster
+// across hosts), else workgroups of 64 output channels, unless only
+// 32-channel workgroups get eight rows (two waves per SIMD); measured on 5x5,
+// C=64: 0.059 -> 0.055 ms.
 const LdsEntry *lds_kernel_for(int f, int c, int c_out) {
     if (c_out % 64 != 0) return lds_entry(f, c, 2);
+    if (const LdsEntry *e = lds_entry(f, c, 4, 2)) return e;
     const LdsEntry *e4 = lds_entry(f, c, 4), *e2 = lds_entry(f, c, 2);
     if (e4 && e4->th < 8 && e2 && e2->th == 8) return e2;
     return e4 ? e4 : e2;

@@ -94,11 +94,12 @@ def test_igemm_full_size(gt, f):
 # Shapes with more tiles than the 256-CU device holds at once, so persistent
 # workgroups run several tiles each, including runs that cross from one
 # column strip (or image) to the next, ragged right and bottom tiles, each
-# weight placement (all in LDS, one slab double-buffered, read from L2) and
-# both workgroup heights (four and eight output rows).
+# weight placement (all in LDS, one slab double-buffered, read from L2),
+# both workgroup heights (four and eight output rows) and two channel groups
+# per workgroup (3x3 with c_out = 64, both channel counts).
 PERSISTENT_CASES = [  # n, h, w, c_in, c_out, f
     (4, 150, 250, 64, 64, 3), (3, 146, 190, 64, 64, 5), (3, 146, 190, 32, 64, 9), (3, 146, 190, 64, 64, 7),
-    (3, 146, 190, 64, 64, 9), (3, 146, 190, 64, 32, 7),
+    (3, 146, 190, 64, 64, 9), (3, 146, 190, 64, 32, 7), (3, 146, 190, 32, 64, 3), (2, 61, 200, 64, 128, 3),
 ]
 
 
