@@ -151,6 +151,12 @@ def igemm_extras(gt, torch, dev, steps=200, energy=True, outputs=None, warmup_s=
                     m = gt.measure_time_energy(p, (64, 1, 1, 1, 0, 0), dx, dw, out, window_s=1.6, discard_s=0.3)
                     r.update(gflops_per_w=round(m["gflops_per_w"], 3), p_median_w=m["p_median_w"],
                              sclk_mhz=round(m["sclk_act_mhz"], 1))
+                    # a compute peak scales with the graphics clock, which these
+                    # loads pull down near the power cap; the HBM peak does not
+                    sclk = m["sclk_act_mhz"]
+                    if r["roofline"]["bound"] != "hbm" and math.isfinite(sclk) and sclk > 0:
+                        r["roofline"].update(clock_mhz_measured=round(sclk, 1), frac_at_measured_clock=round(
+                            r["roofline"]["achieved"] / (r["roofline"]["peak"] * sclk / PEAK_CLOCK_MHZ), 4))
                 except gt.GreentuneError as e:
                     r["energy_error"] = str(e)
             res["%s_f%d" % (name, f)] = r
