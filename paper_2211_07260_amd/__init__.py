@@ -277,7 +277,41 @@ def version():
 
 # ---- the four calls ----
 
+def buffer_extents(problem):
+    """Bytes the dense input, filter and output of a problem span (None for
+    sizes the library rejects anyway)."""
+    p = problem
+    if min(p.n, p.c_in, p.c_out, p.out_h, p.out_w, p.filt_h, p.filt_w) < 1 or min(p.pad_h, p.pad_w) < 0:
+        return None
+    if p.kind == XCORR_F32:
+        return ((p.out_h + p.filt_h - 1) * (p.out_w + p.filt_w - 1) * 4, p.filt_h * p.filt_w * 4,
+                p.out_h * p.out_w * 4)
+    eb = 2 if p.kind == IGEMM_BF16_MFMA else 4
+    h, w = p.out_h + p.filt_h - 1 - 2 * p.pad_h, p.out_w + p.filt_w - 1 - 2 * p.pad_w
+    if h < 1 or w < 1:
+        return None
+    return (p.n * h * w * p.c_in * eb, p.c_out * p.filt_h * p.filt_w * p.c_in * eb, p.n * p.out_h * p.out_w * p.c_out * 4)
+
+
+def check_buffers(problem, inp, filt, out):
+    """Refuse tensors that are not contiguous or end before the problem's
+    dense extent: the kernels read and write that many bytes from each
+    pointer.  (Raw integer pointers are passed through unchecked.)"""
+    ext = buffer_extents(problem)
+    if ext is None:
+        return
+    for t, need, name in zip((inp, filt, out), ext, ("input", "filter", "output")):
+        if not hasattr(t, "is_contiguous"):
+            continue
+        if not t.is_contiguous():
+            raise ValueError("%s tensor must be contiguous" % name)
+        have = t.numel() * t.element_size()
+        if have < need:
+            raise ValueError("%s tensor holds %d bytes; the problem needs %d" % (name, have, need))
+
+
 def conv2d_run(problem, cfg, inp, filt, out, clk=None, stream=None):
+    check_buffers(problem, inp, filt, out)
     _check(_lib.conv2d_run(ctypes.byref(problem), ctypes.byref(as_config(cfg)), clk or clock(),
                            _ptr(inp), _ptr(filt), _ptr(out), _stream(stream)))
 
@@ -285,6 +319,7 @@ def conv2d_run(problem, cfg, inp, filt, out, clk=None, stream=None):
 def conv2d_run_part(problem, cfg, part, n_parts, inp, filt, out, clk=None, stream=None):
     """Part `part` of `n_parts` of conv2d_run (contiguous ranges of output
     tiles; bit-identical to the whole run)."""
+    check_buffers(problem, inp, filt, out)
     _check(_lib.conv2d_run_part(ctypes.byref(problem), ctypes.byref(as_config(cfg)), clk or clock(), int(part),
                                 int(n_parts), _ptr(inp), _ptr(filt), _ptr(out), _stream(stream)))
 
@@ -310,6 +345,7 @@ def tune_space_enumerate(problem, values, max_threads=0, lds_limit=0, dedup_dire
 
 def measure_time_energy(problem, cfg, inp, filt, out, clk=None, window_s=1.0, discard_s=0.3,
                         sample_period_ms=1.0, min_launches=10, warmup_launches=3, stream=None, use_graph=False):
+    check_buffers(problem, inp, filt, out)
     o = MeasureOpts(window_s, discard_s, sample_period_ms, min_launches, warmup_launches, 1 if use_graph else 0)
     m = Measurement()
     _check(_lib.measure_time_energy(ctypes.byref(problem), ctypes.byref(as_config(cfg)), clk or clock(),
@@ -559,6 +595,7 @@ class Batch:
         self.cfg = as_config(cfg)
         items = (BatchItem * len(convs))()
         for k, (di, dw, do, oh, ow, f) in enumerate(convs):
+            check_buffers(xcorr_problem(oh, ow, f, f), di, dw, do)
             items[k] = BatchItem(di.data_ptr(), dw.data_ptr(), do.data_ptr(), oh, ow, f, f)
         self.n = len(convs)
         self.filt = convs[0][5]
@@ -607,6 +644,7 @@ class IgemmBatch:
         self.shape.pad_h = self.shape.pad_w = int(pad)
         items = (BatchItem * len(convs))()
         for k, (di, dw, do, oh, ow) in enumerate(convs):
+            check_buffers(Problem(IGEMM_BF16_MFMA, 1, c_in, c_out, oh, ow, f, f, int(pad), int(pad)), di, dw, do)
             items[k] = BatchItem(di.data_ptr(), dw.data_ptr(), do.data_ptr(), oh, ow, f, f)
         self.n = len(convs)
         nb, tb = ctypes.c_size_t(0), ctypes.c_int64(0)
@@ -641,6 +679,7 @@ def conv2d_run_batched_noalloc(convs, cfg, grid_blocks=0, stream=None):
     Batch.  Calls that overlap on one GPU race on that array."""
     items = (BatchItem * max(1, len(convs)))()
     for k, (di, dw, do, oh, ow, f) in enumerate(convs):
+        check_buffers(xcorr_problem(oh, ow, f, f), di, dw, do)
         items[k] = BatchItem(di.data_ptr(), dw.data_ptr(), do.data_ptr(), oh, ow, f, f)
     _check(_lib.conv2d_run_batched_noalloc(items, len(convs), ctypes.byref(as_config(cfg)), int(grid_blocks),
                                            _stream(stream)))

@@ -46,7 +46,7 @@ def host_only():
 
 def test_gpu_calls_refused_host_only():
     import torch
-    t = torch.zeros(4)
+    t = torch.zeros(16)  # covers the 4x4 input, 3x3 filter and 2x2 output
     with pytest.raises(gt.GreentuneError) as e:
         gt.conv2d_run(gt.xcorr_problem(2, 2, 3, 3), gt.config(), t, t, t, stream=0)
     assert e.value.code == gt.GT_E_STATE
@@ -389,3 +389,25 @@ def test_igemm_batch_pack_host():
                gt.conv_problem(gt.IGEMM_F32_VALU, 1, 1, 1, 32, 64, 5, 5)):
         assert lib.gt_igemm_batch_pack(ctypes.byref(sh), items, len(sides), None, 0, ctypes.byref(nb),
                                        ctypes.byref(tb)) == gt.GT_E_UNSUPPORTED
+
+
+def test_binding_refuses_short_or_strided_tensors():
+    """The binding checks each tensor against the problem's dense extent
+    before a pointer reaches the library (the kernels read and write that
+    many bytes from it)."""
+    import torch
+    p = gt.xcorr_problem(8, 10, 3, 3)
+    assert gt.buffer_extents(p) == (10 * 12 * 4, 9 * 4, 8 * 10 * 4)
+    img, w, out = torch.zeros(10, 12), torch.zeros(3, 3), torch.zeros(8, 10)
+    gt.check_buffers(p, img, w, out)
+    with pytest.raises(ValueError, match="output"):
+        gt.check_buffers(p, img, w, torch.zeros(8, 9))
+    with pytest.raises(ValueError, match="input"):
+        gt.check_buffers(p, torch.zeros(20, 24)[1:11, :12], w, out)  # a strided view
+    big = torch.zeros(10 * 12 + 5)
+    gt.check_buffers(p, big[5:].view(10, 12), w, out)                 # a contiguous view at an offset
+    with pytest.raises(ValueError, match="input"):
+        gt.check_buffers(p, big[6:], w, out)
+    q = gt.Problem(gt.IGEMM_BF16_MFMA, 2, 32, 64, 6, 7, 3, 3, 1, 1)
+    assert gt.buffer_extents(q) == (2 * 6 * 7 * 32 * 2, 64 * 9 * 32 * 2, 2 * 6 * 7 * 64 * 4)
+    assert gt.buffer_extents(gt.xcorr_problem(0, 4, 3, 3)) is None  # the library rejects it itself

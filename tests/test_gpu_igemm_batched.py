@@ -98,9 +98,11 @@ def test_batched_graph_replay(gt):
 
 def test_batch_pack_rejects(gt):
     dev = torch.device("cuda:0")
-    x = torch.zeros(8, 8, 32, dtype=torch.bfloat16, device=dev)
-    w = torch.zeros(32, 3, 3, 32, dtype=torch.bfloat16, device=dev)
-    o = torch.zeros(8, 8, 32, device=dev)
+    # buffers large enough for every shape below: the library, not the
+    # binding's extent check, is what refuses these shapes
+    x = torch.zeros(8 * 8 * 64, dtype=torch.bfloat16, device=dev)
+    w = torch.zeros(64 * 3 * 3 * 64, dtype=torch.bfloat16, device=dev)
+    o = torch.zeros(8 * 8 * 64, device=dev)
     with pytest.raises(gt.GreentuneError) as e:
         gt.IgemmBatch([(x, w, o, 8, 8)], 48, 32, 3, 1)      # c_in not instantiated
     assert e.value.code == gt.GT_E_UNSUPPORTED
