@@ -79,3 +79,33 @@ def test_noalloc_size_limit(gt):
     rc = gt.lib().conv2d_run_batched_noalloc(items, n, ctypes.byref(gt.as_config((16, 1, 1, 1, 0, 0))), 0, None)
     assert rc == gt.GT_E_INVAL
     assert "items" in gt.lib().gt_last_error().decode()
+
+
+def test_noalloc_in_a_captured_graph(gt):
+    """The entry point under HIP graph capture, its callers' case: the
+    descriptors reach the device array through kernel arguments, so every
+    replay rewrites them, also after an eager call in between has filled the
+    array with another batch."""
+    f, cfg = 9, (32, 8, 4, 4, 0, 0)
+    convs, _ = make_convs(f, 70, seed=31, max_side=150)  # two upload chunks
+    ref = with_outputs(convs)
+    gt.Batch(ref, cfg).run()
+    other, _ = make_convs(5, 20, seed=32, max_side=90)
+    other_cfg = (32, 8, 2, 2, 0, 0)
+    gt.conv2d_run_batched_noalloc(other, other_cfg)  # device address looked up before the capture
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    g = gt.Graph(lambda: gt.conv2d_run_batched_noalloc(convs, cfg, stream=side), side)
+    try:
+        for rep in range(3):
+            print("noalloc graph replay %d" % rep, flush=True)
+            for c in convs:
+                c[2].fill_(float("nan"))                 # eager work between replays
+            gt.conv2d_run_batched_noalloc(other, other_cfg)  # refills the descriptor array
+            torch.cuda.synchronize()
+            g.launch()
+            side.synchronize()
+            for k, (c, r) in enumerate(zip(convs, ref)):
+                assert torch.equal(c[2], r[2]), (rep, k)
+    finally:
+        g.close()
