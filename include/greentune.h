@@ -55,8 +55,8 @@ extern "C" {
  *   tile_size_x/y    outputs per thread along x / y (1..8)
  *   use_lds_padding  0/1: pad each LDS row by 4 floats
  *   read_path        0: stage the input halo in LDS; 1: read global memory directly
- * For the implicit-GEMM kinds only block_size_x (and read_path = 0) is used;
- * see conv2d_run. */
+ * The implicit-GEMM kinds ignore it: the library picks their kernel and
+ * workgroup shape from the problem (see conv2d_run). */
 typedef struct {
     int32_t block_size_x, block_size_y, tile_size_x, tile_size_y, use_lds_padding, read_path;
 } gt_conv_config;
@@ -183,7 +183,15 @@ const char *gt_version(void);
 /* Launch one convolution asynchronously on hip_stream.
  * problem/config as above; clock: knob applied first (synchronously, only if
  * it differs from the current setting; GT_CLOCK_DEFAULT never touches DVFS).
- * d_in, d_filt, d_out: device pointers laid out as in gt_problem.
+ * d_in, d_filt, d_out: device pointers laid out as in gt_problem; the
+ * caller keeps them valid until the launch has run.  Every index is a 32-bit
+ * element offset: inputs of 2^31 elements or more are GT_E_INVAL.
+ * Implicit GEMM, BF16 (c_in 32 or 64, c_out a multiple of 32, square
+ * filters): filters of 1, 3, 5, 7, 9 (and 17 for c_in 32) with a 16-byte
+ * aligned output run the LDS-staged MFMA kernel (workgroups of 4 or 8 output
+ * rows x 64 pixels x 32 or 64 output channels, persistent over tiles); other
+ * filter sizes and unaligned outputs the global-load MFMA kernel.  FP32
+ * (c_in 32 or 64, c_out a multiple of 64): the register-tiled vector kernel.
  * Errors: GT_E_INVAL (null pointer, sizes), GT_E_UNSUPPORTED (config outside
  * the restricted space or filter width not instantiated: single-channel
  * filt_w in {3,5,9,17} with tile sizes 1..8), GT_E_PERM (clock knob
