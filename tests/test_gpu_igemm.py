@@ -45,6 +45,9 @@ CASES = [  # n, h, w, c_in, c_out, f
     (2, 9, 13, 64, 64, 3), (1, 16, 16, 64, 64, 5), (3, 7, 11, 32, 32, 3), (2, 12, 10, 32, 64, 5),
     (1, 5, 37, 64, 32, 1), (1, 8, 9, 64, 128, 7), (1, 3, 3, 32, 32, 5), (2, 20, 17, 64, 64, 3),
     (1, 20, 23, 32, 32, 9), (1, 18, 19, 32, 32, 17), (1, 12, 40, 64, 64, 9), (2, 9, 9, 32, 64, 17),
+    # three 32-channel blocks along c_out (c_out not a multiple of 64), and filter sizes without an
+    # unrolled instance (the runtime-size kernels)
+    (1, 20, 30, 64, 96, 3), (2, 13, 70, 32, 96, 5), (1, 11, 17, 32, 32, 11), (1, 9, 21, 64, 64, 13),
 ]
 
 
