@@ -425,5 +425,6 @@ def benchmark(n_req=8000, seed=0, util=0.7, mem_budget=64 << 30, discard_s=0.3, 
            "mix": {"xcorr_f32": sum(r.kind == "xcorr_f32" for r in done),
                    "conv_bf16": sum(r.kind == "conv_bf16" for r in done)}}
     rep.update(latency=latency_stats(done),
+               latency_by_kind={k: latency_stats([r for r in done if r.kind == k]) for k in ("xcorr_f32", "conv_bf16")},
                energy=energy_stats(samples, t_start, t_stop, len(done), discard_s=discard_s))
     return rep
