@@ -163,7 +163,42 @@ def igemm_extras(gt, torch, dev, steps=200, energy=True, outputs=None, warmup_s=
             if outputs is not None:
                 torch.cuda.synchronize()
                 outputs["%s_f%d" % (name, f)] = out.cpu().numpy()
+            if kind == gt.IGEMM_BF16_MFMA and energy:
+                res["%s_f%d_rows" % (name, f)] = mfma_rows_variants(gt, torch, p, dx, dw, out, steps, warmup_s)
     return res
+
+
+def mfma_rows_variants(gt, torch, p, dx, dw, out, steps, warmup_s):
+    """The BF16 kernel's two instances (4 or 8 output rows per tile, the
+    tile_size_y tunable) measured for time and energy: the time-optimal and
+    the energy-optimal one, the tuner's two objectives on this path."""
+    rep = {}
+    for rows in (4, 8):
+        cfg = (64, 1, 1, rows, 0, 0)
+        t_w0 = time.perf_counter()
+        while time.perf_counter() - t_w0 < warmup_s:
+            for _ in range(10):
+                gt.conv2d_run(p, cfg, dx, dw, out)
+            torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            gt.conv2d_run(p, cfg, dx, dw, out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        try:
+            m = gt.measure_time_energy(p, cfg, dx, dw, out, window_s=1.6, discard_s=0.3)
+        except gt.GreentuneError as e:
+            return {"energy_error": str(e)}
+        rep[str(rows)] = {"ms": round(ms, 5), "tflops": round(gt.problem_flops(p) / ms / 1e9, 2),
+                          "gflops_per_w": round(m["gflops_per_w"], 3), "p_median_w": m["p_median_w"],
+                          "sclk_mhz": round(m["sclk_act_mhz"], 1)}
+    rep["time_optimal_rows"] = int(min(("4", "8"), key=lambda k: rep[k]["ms"]))
+    rep["energy_optimal_rows"] = int(max(("4", "8"), key=lambda k: rep[k]["gflops_per_w"]))
+    rep["energy_optimal_vs_time_optimal_gflops_per_w"] = round(
+        rep[str(rep["energy_optimal_rows"])]["gflops_per_w"] / rep[str(rep["time_optimal_rows"])]["gflops_per_w"], 4)
+    return rep
 
 
 def multichannel_roofline(bf16, f, flops, ms, n=16, side=128, c=64):

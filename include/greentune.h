@@ -55,8 +55,15 @@ extern "C" {
  *   tile_size_x/y    outputs per thread along x / y (1..8)
  *   use_lds_padding  0/1: pad each LDS row by 4 floats
  *   read_path        0: stage the input halo in LDS; 1: read global memory directly
- * The implicit-GEMM kinds ignore it: the library picks their kernel and
- * workgroup shape from the problem (see conv2d_run). */
+ * The implicit-GEMM kinds take their kernel from the problem (see
+ * conv2d_run), with one tunable: for GT_IGEMM_BF16_MFMA, tile_size_y = 4 or
+ * 8 asks for the LDS-staged kernel with that many output rows per workgroup
+ * tile where the shape has both (e.g. 3x3 with c_out a multiple of 64: 4
+ * rows of two 32-channel groups, the default, or 8 rows of 64 channels;
+ * 5x5 with c_in 64: 8 rows of 32 channels, the default, or 4 rows of 64).
+ * The fastest instance is the default; it need not be the most
+ * energy-efficient one.  Any other value, and the other fields, leave the
+ * choice to the library; GT_IGEMM_F32_VALU ignores the config. */
 typedef struct {
     int32_t block_size_x, block_size_y, tile_size_x, tile_size_y, use_lds_padding, read_path;
 } gt_conv_config;

@@ -1029,12 +1029,26 @@ const LdsEntry *lds_entry(int f, int c, int nt, int g = 1) {
 // across hosts), else workgroups of 64 output channels, unless only
 // 32-channel workgroups get eight rows (two waves per SIMD); measured on 5x5,
 // C=64: 0.059 -> 0.055 ms.
-const LdsEntry *lds_kernel_for(int f, int c, int c_out) {
-    if (c_out % 64 != 0) return lds_entry(f, c, 2);
-    if (const LdsEntry *e = lds_entry(f, c, 4, 2)) return e;
-    const LdsEntry *e4 = lds_entry(f, c, 4), *e2 = lds_entry(f, c, 2);
-    if (e4 && e4->th < 8 && e2 && e2->th == 8) return e2;
-    return e4 ? e4 : e2;
+// rows = 4 or 8 asks for the instance with that many output rows per tile
+// where the shape has one (the time-optimal instance is not always the
+// energy-optimal one); any other value takes the default order.
+const LdsEntry *lds_kernel_for(int f, int c, int c_out, int rows = 0) {
+    const LdsEntry *cand[3] = {nullptr, nullptr, nullptr};
+    if (c_out % 64 != 0) {
+        cand[0] = lds_entry(f, c, 2);
+    } else {
+        const LdsEntry *e4 = lds_entry(f, c, 4), *e2 = lds_entry(f, c, 2);
+        const bool two_first = e4 && e4->th < 8 && e2 && e2->th == 8;
+        cand[0] = lds_entry(f, c, 4, 2);
+        cand[1] = two_first ? e2 : e4;
+        cand[2] = two_first ? e4 : e2;
+    }
+    if (rows == 4 || rows == 8)
+        for (const LdsEntry *e : cand)
+            if (e && e->th == rows) return e;
+    for (const LdsEntry *e : cand)
+        if (e) return e;
+    return nullptr;
 }
 
 }  // namespace
@@ -1061,7 +1075,7 @@ int validate_igemm(const gt_problem &p, const gt_conv_config &) {
     return GT_OK;
 }
 
-int launch_igemm(const gt_problem &p, const gt_conv_config &, const void *in, const void *w, void *out,
+int launch_igemm(const gt_problem &p, const gt_conv_config &c, const void *in, const void *w, void *out,
                  hipStream_t s, int part, int n_parts) {
     if ((((uintptr_t)in) | ((uintptr_t)w)) & 15)
         return set_error(GT_E_INVAL, "igemm: input and weights must be 16-byte aligned");
@@ -1081,7 +1095,7 @@ int launch_igemm(const gt_problem &p, const gt_conv_config &, const void *in, co
     a.m_total = p.n * p.out_h * p.out_w;
     void *args[] = {&a};
     if (p.kind == GT_IGEMM_BF16_MFMA && p.filt_h == p.filt_w && ((uintptr_t)out & 15) == 0) {
-        if (const LdsEntry *e = lds_kernel_for(p.filt_h, p.c_in, p.c_out)) {
+        if (const LdsEntry *e = lds_kernel_for(p.filt_h, p.c_in, p.c_out, c.tile_size_y)) {
             const int64_t all_tiles = (int64_t)p.n * ((p.out_h + e->th - 1) / e->th) * ((p.out_w + kLdsTW - 1) / kLdsTW);
             if (all_tiles >= ((int64_t)1 << 31)) return set_error(GT_E_INVAL, "igemm: too many tiles");
             // part k of n: tiles [all * k / n, all * (k + 1) / n)

@@ -205,3 +205,30 @@ def test_parts_full_size(gt, f):
         gt.conv2d_run_part(p, (64, 1, 1, 1, 0, 0), k, 7, dx, dw, parts, stream=streams[k % 2])
     torch.cuda.synchronize()
     assert torch.equal(parts, whole)
+
+
+@pytest.mark.parametrize("case", [(3, 146, 190, 64, 64, 3), (2, 61, 200, 64, 128, 3), (3, 146, 190, 64, 64, 5),
+                                  (2, 40, 70, 64, 128, 5)])
+def test_rows_per_tile_variants(gt, case):
+    """tile_size_y = 4 or 8 picks the LDS-staged instance with that many
+    output rows per tile (two 32-channel groups of four rows or one 64-channel
+    group of eight for 3x3; 64 channels of four rows or 32 of eight for 5x5):
+    both match the oracle and, accumulating in the same order, each other
+    bit for bit; any other value is the default instance."""
+    n, h, w, ci, co, f = case
+    x, wt = conv_inputs(n, h, w, ci, co, f, f, seed=40 + f)
+    pad = (f - 1) // 2
+    ref = oracle.conv_nhwc(x.float().numpy(), wt.float().numpy(), pad, pad)
+    dev = torch.device("cuda:0")
+    dx, dw = x.to(dev).contiguous(), wt.to(dev).contiguous()
+    p = gt.Problem(gt.IGEMM_BF16_MFMA, n, ci, co, h, w, f, f, pad, pad)
+    outs = {}
+    for rows in (4, 8, 1):
+        print("case: rows", rows, case, flush=True)
+        out = torch.full((n, h, w, co), float("nan"), dtype=torch.float32, device=dev)
+        gt.conv2d_run(p, (64, 1, 1, rows, 0, 0), dx, dw, out)
+        torch.cuda.synchronize()
+        outs[rows] = out.cpu().numpy()
+        assert oracle.max_rel_err(outs[rows], ref) <= TOL[1], rows
+    assert np.array_equal(outs[4].view(np.uint32), outs[8].view(np.uint32))
+    assert np.array_equal(outs[1].view(np.uint32), outs[4].view(np.uint32))
