@@ -335,7 +335,9 @@ def main():
             if c is None:
                 continue
             try:
-                m = gt.measure_time_energy(prob, c, d_in, d_w, out, window_s=2.0, discard_s=0.4)
+                # 2.2 s kept: at least two updates of the once-a-second energy
+                # counter, for its cross-check of median power x time
+                m = gt.measure_time_energy(prob, c, d_in, d_w, out, window_s=2.6, discard_s=0.4)
                 energy[name] = {"config": list(c), "gflops_per_w": m["gflops_per_w"], "gflops": m["gflops"],
                                 "p_median_w": m["p_median_w"], "e_run_j": m["e_run_j"],
                                 "e_run_counter_j": m["e_run_counter_j"], "sclk_act_mhz": m["sclk_act_mhz"],
